@@ -1,0 +1,147 @@
+/*
+ * rtsgrid: convolutional gridding and degridding of radio visibilities on AMD
+ * MI355X (gfx950).  C ABI of librtsgrid.so.
+ *
+ * What is computed (Edgar et al., "Enabling a High Throughput Real Time Data
+ * Pipeline for a Large Radio Telescope Array with GPUs", Section 5, Eq. (1)):
+ * every visibility V_i at (u_i, v_i) is convolved with a compact gridding
+ * function and added onto a regular uv grid,
+ *     G[c][y][x] = sum_i w_i V_i k(y - y_i) k(x - x_i),
+ * where k is a Kaiser-Bessel window of support W cells sampled at OS phases per
+ * cell (the nearest phase is used) and k vanishes at and beyond W/2.  Degridding
+ * is the adjoint without weights,
+ *     M_i = sum_{x,y} k(y - y_i) k(x - x_i) G[c][y][x].
+ * Coordinates: x_i = u_i f_c / (c du) + N/2 cells (pixel N/2 is u = 0), snapped to
+ * 1/OS cell by rounding half up; this is the only FP64 arithmetic, everything
+ * after it is FP32.  A sample is valid iff its weight (at plan time) is non-zero
+ * and every tap lies on the grid; invalid samples contribute nothing and predict 0.
+ *
+ * Layouts (row-major, C-contiguous):
+ *   uvw      double  [B][T][3]   metres, device memory
+ *   freq_hz  double  [C]         host memory
+ *   vis, model       [C][B][T]   complex64 as interleaved float (re, im), device
+ *   weights  float   [C][B][T]   device; 0 marks a flagged sample
+ *   grid             [C][N][N]   complex64 as interleaved float, [channel][v][u], device
+ * A baseline's T time samples are contiguous: the tiled kernels read each
+ * baseline's track as one run.
+ *
+ * Ownership: the caller owns every buffer passed in; a plan owns its own
+ * workspace (kernel table, per-sample packed coordinates, the tile-sorted work
+ * list).  uvw and weights may be freed once rts_grid_plan has returned AND its
+ * stream has been synchronised.
+ *
+ * Errors: every entry point returns an rts_status and never aborts.  Arguments
+ * are validated on the host before any HIP call.  On failure the message is
+ * available from rts_last_error() (thread-local).  NaN or Inf in vis / weights
+ * propagate; NaN or Inf in uvw make the sample invalid.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  All calls
+ * enqueue asynchronously on it; only rts_grid_plan synchronises it (once, to
+ * size the work list).  One plan must not be used concurrently on two streams.
+ */
+#ifndef RTSGRID_H
+#define RTSGRID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rts_plan_s *rts_plan_t;
+
+typedef enum {
+  RTS_OK = 0,
+  RTS_E_INVALID = 1,      /* bad argument (null pointer, size out of range, ...) */
+  RTS_E_NOMEM = 2,        /* device or host allocation failed */
+  RTS_E_HIP = 3,          /* a HIP runtime call failed */
+  RTS_E_UNSUPPORTED = 4,  /* valid request this build does not implement */
+} rts_status;
+
+typedef enum { RTS_PREC_FP32 = 0 } rts_precision;
+
+typedef struct {
+  int32_t n_grid;       /* N: grid edge in cells, even, 16 <= N <= 8192                  */
+  int32_t support;      /* W: taps per axis, 2 <= W <= 16                                */
+  int32_t oversample;   /* OS: kernel phases per cell, 1 <= OS <= 64                     */
+  int32_t n_chan;       /* C >= 1                                                         */
+  int32_t n_base;       /* B >= 1                                                         */
+  int32_t n_time;       /* T >= 1; C*B*T*(1+conjugate) < 2^31                            */
+  double cell_lambda;   /* du > 0: uv cell size in wavelengths                           */
+  double beta;          /* Kaiser-Bessel shape; <= 0 selects 2.34 * W                     */
+  int32_t conjugate;    /* 1: also grid conj(w V) at (-u, -v) (rts_grid only)             */
+  int32_t tile;         /* uv tile edge in cells: divides N, >= W+1, <= 128; 0 = choose   */
+  int32_t precision;    /* rts_precision                                                 */
+  int32_t reserved;     /* must be 0                                                     */
+} rts_params;
+
+typedef struct {
+  int64_t n_samples;    /* C*B*T                                                         */
+  int64_t n_valid;      /* samples with w != 0 and all taps on the grid                   */
+  int64_t n_flagged;    /* samples with w == 0                                            */
+  int64_t n_offgrid;    /* samples with w != 0 but a tap off the grid (or non-finite uvw) */
+  int64_t n_segments;   /* runs of one baseline's samples sharing a (W+1)^2 cell window   */
+  int64_t n_listings;   /* (segment, tile) pairs in the work list                        */
+  int64_t workspace_bytes;
+  int32_t tile;         /* tile edge chosen                                               */
+  int32_t seg_max;      /* most samples per segment                                       */
+} rts_plan_info;
+
+/*
+ * Build a gridding plan (Section 5.2: visibilities are binned by uv tile and each
+ * tile's work is listed, so that one workgroup owns each tile of the output).
+ * From uvw, the channel frequencies and the weights it computes every sample's
+ * snapped FP64 coordinates, groups each baseline's consecutive samples into
+ * segments, and sorts the segments by (channel, tile) with a counting sort.
+ * Synchronises `stream` once.  *out receives the plan (NULL on failure).
+ */
+rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double *uvw_m,
+                         const double *freq_hz, const float *weights, void *stream);
+
+/* Eq. (1): grid[c] = sum_i w_i V_i k k over valid samples (and conj(w V) at -uv
+ * when the plan was built with conjugate=1).  `grid` [C][N][N] is overwritten. */
+rts_status rts_grid(rts_plan_t plan, const float *vis, const float *weights, float *grid,
+                    void *stream);
+
+/* Adjoint of Eq. (1) without weights: vis_out[c][b][t] = sum k k G at the +uv
+ * position of each valid sample, 0 for invalid samples.  All C*B*T entries are
+ * written. */
+rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *stream);
+
+/* Fused residual step: M = degrid(grid_in); r = V - M (0 where invalid);
+ * grid_out = grid(r, w); chi2 = sum_i w_i |r_i|^2 (FP64).  model_out (C*B*T
+ * complex64) and chi2_out (one double in device memory) may be NULL.  grid_in and
+ * grid_out must not overlap.  Plans built with conjugate=1 return RTS_E_UNSUPPORTED. */
+rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weights,
+                           const float *grid_in, float *model_out, float *grid_out,
+                           double *chi2_out, void *stream);
+
+/* a1 exposed for exact testing: out[c][b][t] = {xs, ys, valid} (int32) where
+ * (xs, ys) are the snapped oversampled coordinates floor((u f/(c du) + N/2) OS + 1/2)
+ * of the +uv copy (0 when non-finite) and valid follows the rule above.
+ * `out` is device memory of C*B*T*3 int32. */
+rts_status rts_compute_coords(const rts_params *params, const double *uvw_m,
+                              const double *freq_hz, const float *weights, int32_t *out,
+                              void *stream);
+
+/* Copy the FP32 kernel table tab[p][j] = k(t_j - r_p/OS) (OS rows, W columns; rows
+ * are phases r0..r0+OS-1, columns taps t0..t0+W-1 with r0 = -(OS/2), t0 = -(W-1)/2
+ * for odd W and r0 = 0, t0 = -W/2+1 for even W) into host memory `tab`
+ * of `capacity` floats. */
+rts_status rts_plan_get_table(rts_plan_t plan, float *tab, int64_t capacity);
+
+rts_status rts_plan_get_info(rts_plan_t plan, rts_plan_info *info);
+
+/* Release the plan and its workspace (waits for the device). NULL is accepted. */
+rts_status rts_plan_destroy(rts_plan_t plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rts_last_error(void);
+
+/* Library version string. */
+const char *rts_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTSGRID_H */

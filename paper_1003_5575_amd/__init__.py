@@ -1,0 +1,207 @@
+"""rtsgrid for AMD MI355X: convolutional gridding / degridding of radio visibilities.
+
+A thin binding over librtsgrid.so (C ABI, hand-written HIP kernels for gfx950).
+PyTorch supplies device memory and streams only; every step of the computation
+runs in the library's kernels.  See include/rtsgrid.h for the exact semantics.
+
+    plan = GridPlan(uvw, freq_hz, weights, n_grid=2048, cell_lambda=du)
+    G = plan.grid(vis, weights)                 # Eq. (1)
+    M = plan.degrid(G)                          # adjoint
+    M, G_out, chi2 = plan.grid_degrid(vis, weights, G_in)
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import RtsError, RtsParams, RtsPlanInfo  # noqa: F401
+
+__all__ = ["GridPlan", "compute_coords", "RtsError", "library_path", "version"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def version() -> str:
+    return _lib.load().rts_version().decode()
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _check_dev(t, name, dtype, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def make_params(n_grid, cell_lambda, support, oversample, n_chan, n_base, n_time, beta=None,
+                conjugate=False, tile=0) -> RtsParams:
+    p = RtsParams()
+    p.n_grid, p.support, p.oversample = int(n_grid), int(support), int(oversample)
+    p.n_chan, p.n_base, p.n_time = int(n_chan), int(n_base), int(n_time)
+    p.cell_lambda = float(cell_lambda)
+    p.beta = float(beta) if beta is not None else 0.0
+    p.conjugate = int(bool(conjugate))
+    p.tile = int(tile)
+    p.precision = 0
+    p.reserved = 0
+    return p
+
+
+class GridPlan:
+    """A gridding plan over one cadence: uvw [B][T][3] (float64, metres, device),
+    freq_hz [C] (host sequence), weights [C][B][T] (float32, device; 0 = flagged)."""
+
+    def __init__(self, uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversample=8,
+                 beta=None, conjugate=False, tile=0, stream=None):
+        torch = _torch()
+        lib = _lib.load()
+        _check_dev(uvw, "uvw", torch.float64)
+        if uvw.dim() != 3 or uvw.shape[2] != 3:
+            raise ValueError("uvw must be [B][T][3]")
+        B, T = int(uvw.shape[0]), int(uvw.shape[1])
+        freq = [float(f) for f in freq_hz]
+        C = len(freq)
+        _check_dev(weights, "weights", torch.float32, (C, B, T))
+        self.params = make_params(n_grid, cell_lambda, support, oversample, C, B, T, beta, conjugate, tile)
+        self.C, self.B, self.T, self.N = C, B, T, int(n_grid)
+        self.device = uvw.device
+        self._freq = (ctypes.c_double * C)(*freq)
+        h = ctypes.c_void_p()
+        _lib.check(lib.rts_grid_plan(ctypes.byref(h), ctypes.byref(self.params), _ptr(uvw),
+                                     ctypes.cast(self._freq, ctypes.c_void_p), _ptr(weights), _stream(stream)),
+                   "rts_grid_plan")
+        self._h = h
+
+    # ------------------------------------------------------------------ queries
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise RuntimeError("plan has been destroyed")
+        return self._h
+
+    @property
+    def info(self) -> dict:
+        inf = RtsPlanInfo()
+        _lib.check(_lib.load().rts_plan_get_info(self.handle, ctypes.byref(inf)), "rts_plan_get_info")
+        return {k: getattr(inf, k) for k, _ in RtsPlanInfo._fields_}
+
+    def table(self):
+        import numpy as np
+        n = self.params.oversample * self.params.support
+        buf = np.zeros(n, np.float32)
+        _lib.check(_lib.load().rts_plan_get_table(self.handle, ctypes.c_void_p(buf.ctypes.data), n),
+                   "rts_plan_get_table")
+        return buf.reshape(self.params.oversample, self.params.support)
+
+    # -------------------------------------------------------------- operations
+    def _vis_shape(self):
+        return (self.C, self.B, self.T)
+
+    def _grid_shape(self):
+        return (self.C, self.N, self.N)
+
+    def grid(self, vis, weights, out=None, stream=None):
+        """Eq. (1): complex64 [C][N][N] (overwritten)."""
+        torch = _torch()
+        _check_dev(vis, "vis", torch.complex64, self._vis_shape())
+        _check_dev(weights, "weights", torch.float32, self._vis_shape())
+        if out is None:
+            out = torch.empty(self._grid_shape(), dtype=torch.complex64, device=vis.device)
+        _check_dev(out, "out", torch.complex64, self._grid_shape())
+        _lib.check(_lib.load().rts_grid(self.handle, _ptr(vis), _ptr(weights), _ptr(out), _stream(stream)),
+                   "rts_grid")
+        return out
+
+    def degrid(self, grid, out=None, stream=None):
+        """Adjoint (no weights): complex64 [C][B][T], 0 at invalid samples."""
+        torch = _torch()
+        _check_dev(grid, "grid", torch.complex64, self._grid_shape())
+        if out is None:
+            out = torch.empty(self._vis_shape(), dtype=torch.complex64, device=grid.device)
+        _check_dev(out, "out", torch.complex64, self._vis_shape())
+        _lib.check(_lib.load().rts_degrid(self.handle, _ptr(grid), _ptr(out), _stream(stream)), "rts_degrid")
+        return out
+
+    def grid_degrid(self, vis, weights, grid_in, model_out=True, grid_out=None, chi2_out=True,
+                    stream=None):
+        """Fused residual step.  Returns (model or None, grid_out, chi2 tensor or None)."""
+        torch = _torch()
+        _check_dev(vis, "vis", torch.complex64, self._vis_shape())
+        _check_dev(weights, "weights", torch.float32, self._vis_shape())
+        _check_dev(grid_in, "grid_in", torch.complex64, self._grid_shape())
+        dev = vis.device
+        if model_out is True:
+            model_out = torch.empty(self._vis_shape(), dtype=torch.complex64, device=dev)
+        elif model_out is False:
+            model_out = None
+        if model_out is not None:
+            _check_dev(model_out, "model_out", torch.complex64, self._vis_shape())
+        if grid_out is None:
+            grid_out = torch.empty(self._grid_shape(), dtype=torch.complex64, device=dev)
+        _check_dev(grid_out, "grid_out", torch.complex64, self._grid_shape())
+        if chi2_out is True:
+            chi2_out = torch.empty((), dtype=torch.float64, device=dev)
+        elif chi2_out is False:
+            chi2_out = None
+        if chi2_out is not None:
+            _check_dev(chi2_out, "chi2_out", torch.float64)
+        _lib.check(_lib.load().rts_grid_degrid(self.handle, _ptr(vis), _ptr(weights), _ptr(grid_in),
+                                               _ptr(model_out), _ptr(grid_out), _ptr(chi2_out),
+                                               _stream(stream)), "rts_grid_degrid")
+        return model_out, grid_out, chi2_out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.load().rts_plan_destroy(self._h), "rts_plan_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def compute_coords(uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversample=8, stream=None):
+    """Snapped oversampled coordinates int32 [C][B][T][3] = (xs, ys, valid) of the +uv copy."""
+    torch = _torch()
+    _check_dev(uvw, "uvw", torch.float64)
+    B, T = int(uvw.shape[0]), int(uvw.shape[1])
+    freq = [float(f) for f in freq_hz]
+    C = len(freq)
+    _check_dev(weights, "weights", torch.float32, (C, B, T))
+    p = make_params(n_grid, cell_lambda, support, oversample, C, B, T)
+    fr = (ctypes.c_double * C)(*freq)
+    out = torch.empty((C, B, T, 3), dtype=torch.int32, device=uvw.device)
+    _lib.check(_lib.load().rts_compute_coords(ctypes.byref(p), _ptr(uvw), ctypes.cast(fr, ctypes.c_void_p),
+                                              _ptr(weights), _ptr(out), _stream(stream)), "rts_compute_coords")
+    return out

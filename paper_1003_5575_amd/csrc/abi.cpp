@@ -1,0 +1,410 @@
+// Host side of librtsgrid: argument validation, the Kaiser-Bessel table, plan
+// workspace management and the extern "C" entry points declared in rtsgrid.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "internal.h"
+
+namespace rts {
+
+static thread_local std::string g_error;
+
+void set_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+}
+
+namespace {
+
+#define RTS_HIP(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      set_error("%s failed: %s", #expr, hipGetErrorString(e_));                         \
+      return e_ == hipErrorOutOfMemory ? RTS_E_NOMEM : RTS_E_HIP;                       \
+    }                                                                                   \
+  } while (0)
+
+#define RTS_REQUIRE(cond, ...)   \
+  do {                           \
+    if (!(cond)) {               \
+      set_error(__VA_ARGS__);    \
+      return RTS_E_INVALID;      \
+    }                            \
+  } while (0)
+
+// Modified Bessel function of the first kind, order 0, from its power series
+// sum_k ((x/2)^2)^k / (k!)^2 (all terms positive, so no cancellation).
+double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 500; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+// Kaiser-Bessel window of support W, zero at and beyond |t| = W/2.
+double kaiser_bessel(double t, int W, double beta) {
+  if (!(std::fabs(t) < 0.5 * W)) return 0.0;
+  const double a = 2.0 * t / W;
+  return bessel_i0(beta * std::sqrt(1.0 - a * a)) / bessel_i0(beta);
+}
+
+bool aligned(const void *p, size_t n) { return ((uintptr_t)p % n) == 0; }
+
+rts_status validate(const rts_params *p) {
+  RTS_REQUIRE(p != nullptr, "params is NULL");
+  RTS_REQUIRE(p->n_grid >= 16 && p->n_grid <= kMaxN && p->n_grid % 2 == 0,
+              "n_grid must be even and in [16, %d] (got %d)", kMaxN, p->n_grid);
+  RTS_REQUIRE(p->support >= 2 && p->support <= kMaxW, "support must be in [2, %d] (got %d)", kMaxW,
+              p->support);
+  RTS_REQUIRE(p->oversample >= 1 && p->oversample <= kMaxOS, "oversample must be in [1, %d] (got %d)",
+              kMaxOS, p->oversample);
+  RTS_REQUIRE(p->n_chan >= 1 && p->n_base >= 1 && p->n_time >= 1,
+              "n_chan, n_base and n_time must be >= 1");
+  RTS_REQUIRE(std::isfinite(p->cell_lambda) && p->cell_lambda > 0.0, "cell_lambda must be > 0");
+  RTS_REQUIRE(std::isfinite(p->beta), "beta must be finite");
+  RTS_REQUIRE(p->conjugate == 0 || p->conjugate == 1, "conjugate must be 0 or 1");
+  RTS_REQUIRE(p->precision == RTS_PREC_FP32, "precision %d is not available", p->precision);
+  RTS_REQUIRE(p->reserved == 0, "reserved must be 0");
+  const int64_t n = (int64_t)p->n_chan * p->n_base * p->n_time * (1 + p->conjugate);
+  RTS_REQUIRE(n < ((int64_t)1 << 31), "n_chan*n_base*n_time*(1+conjugate) must be < 2^31");
+  RTS_REQUIRE(p->n_grid >= p->support + 2, "n_grid must be at least support + 2");
+  if (p->tile != 0) {
+    RTS_REQUIRE(p->tile >= p->support + 1 && p->tile <= kMaxTile && p->tile % 2 == 0 &&
+                    p->n_grid % p->tile == 0,
+                "tile must be even, divide n_grid, and lie in [support+1, %d] (got %d)", kMaxTile,
+                p->tile);
+  }
+  return RTS_OK;
+}
+
+int choose_tile(int N, int WN) {
+  // 64 balances window duplication across tile edges ((64+W)^2/64^2) against LDS
+  // per workgroup (32 KiB of complex FP32); fall back to the nearest legal size.
+  const int prefs[] = {64, 128, 32, 16};
+  for (int t : prefs)
+    if (t >= WN && N % t == 0) return t;
+  for (int t = kMaxTile; t >= WN; t -= 2)
+    if (N % t == 0) return t;
+  return 0;
+}
+
+int choose_seg_max(int W, int T) {
+  if (W <= 8) return T <= 4 ? 4 : 8;
+  if (W <= 12) return 4;
+  return 2;
+}
+
+void fill_tables(Plan &P) {
+  const int W = P.W, OS = P.OS;
+  P.tab.assign((size_t)OS * W, 0.0f);
+  for (int p = 0; p < OS; ++p)
+    for (int j = 0; j < W; ++j) {
+      const int r = P.r0 + p, t = j - P.h_lo;
+      P.tab[(size_t)p * W + j] = (float)kaiser_bessel((double)t - (double)r / OS, W, P.beta);
+    }
+  // Extended table over the (W+1)-wide window: row s = d*OS + p holds the weights
+  // of window columns 0..W for a sample whose cell is d in {0,1} past the window's
+  // first tap position, with phase row p.
+  P.tabE.assign((size_t)2 * OS * P.WNP, 0.0f);
+  for (int d = 0; d < 2; ++d)
+    for (int p = 0; p < OS; ++p)
+      for (int i = 0; i < P.WN; ++i) {
+        const int j = i - d;
+        if (j >= 0 && j < W) P.tabE[(size_t)(d * OS + p) * P.WNP + i] = P.tab[(size_t)p * W + j];
+      }
+}
+
+void free_plan(Plan *P) {
+  if (!P) return;
+  hipFree(P->d_tabE);
+  hipFree(P->d_scale);
+  hipFree(P->d_coords);
+  hipFree(P->d_list);
+  hipFree(P->d_tile_off);
+  hipFree(P->d_cursor);
+  hipFree(P->d_scan_tmp);
+  hipFree(P->d_stats);
+  hipFree(P->d_chi2_part);
+  delete P;
+}
+
+PlanArgs plan_args(const Plan &P, const double *uvw, const float *w) {
+  PlanArgs a{};
+  a.uvw = uvw;
+  a.scale = P.d_scale;
+  a.w = w;
+  a.coords = P.d_coords;
+  a.list = P.d_list;
+  a.counts = P.d_cursor;
+  a.stats = P.d_stats;
+  a.N = P.N; a.W = P.W; a.OS = P.OS; a.WN = P.WN; a.r0 = P.r0; a.h_lo = P.h_lo;
+  a.tile = P.tile; a.nT = P.nT; a.nT2 = P.nT2;
+  a.C = P.C; a.B = P.B; a.T = P.T; a.ncopy = P.ncopy; a.seg_max = P.seg_max;
+  // LDS histogram over the channels of a workgroup when it fits in 32 KiB
+  if (P.nT2 <= 8192) {
+    a.use_lds = 1;
+    a.cg = std::max(1, std::min(8, 8192 / P.nT2));
+  } else {
+    a.use_lds = 0;
+    a.cg = 8;
+  }
+  return a;
+}
+
+TileArgs tile_args(const Plan &P) {
+  TileArgs a{};
+  a.list = P.d_list;
+  a.tile_off = P.d_tile_off;
+  a.coords = P.d_coords;
+  a.tabE = P.d_tabE;
+  a.chi2_part = P.d_chi2_part;
+  a.N = P.N; a.tile = P.tile; a.nT = P.nT; a.nT2 = P.nT2; a.nkeys = (int)P.nkeys;
+  a.B = P.B; a.T = P.T; a.ncopy = P.ncopy;
+  a.OS2 = 2 * P.OS; a.WNP = P.WNP;
+  return a;
+}
+
+template <class T>
+hipError_t dalloc(T **p, size_t n) {
+  return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+rts_status check_plan(rts_plan_t plan) {
+  RTS_REQUIRE(plan != nullptr, "plan is NULL");
+  return RTS_OK;
+}
+
+}  // namespace
+
+bool tile_supported(int W, int seg_max) {
+  if (W < 2 || W > kMaxW) return false;
+  if (W <= 8) return seg_max == 4 || seg_max == 8;
+  if (W <= 12) return seg_max == 4;
+  return seg_max == 2;
+}
+
+hipError_t launch_tile(int mode, const Plan &P, const TileArgs &a, hipStream_t s) {
+  switch (mode) {
+    case kGrid: return launch_tile_mode<kGrid>(P, a, s);
+    case kDegrid: return launch_tile_mode<kDegrid>(P, a, s);
+    default: return launch_tile_mode<kFused>(P, a, s);
+  }
+}
+
+}  // namespace rts
+
+using namespace rts;
+
+
+extern "C" {
+
+const char *rts_last_error(void) { return g_error.c_str(); }
+
+const char *rts_version(void) { return "rtsgrid 0.1 (gfx950)"; }
+
+rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double *uvw_m,
+                         const double *freq_hz, const float *weights, void *stream) {
+  RTS_REQUIRE(out != nullptr, "out is NULL");
+  *out = nullptr;
+  if (rts_status st = validate(params)) return st;
+  RTS_REQUIRE(uvw_m && freq_hz && weights, "uvw_m, freq_hz and weights must be non-NULL");
+  RTS_REQUIRE(aligned(uvw_m, 8) && aligned(weights, 4), "uvw_m / weights are misaligned");
+  for (int c = 0; c < params->n_chan; ++c)
+    RTS_REQUIRE(std::isfinite(freq_hz[c]) && freq_hz[c] > 0.0, "freq_hz[%d] must be > 0", c);
+
+  std::unique_ptr<Plan, void (*)(Plan *)> P(new (std::nothrow) Plan(), [](Plan *p) { free_plan(p); });
+  if (!P) {
+    set_error("host allocation failed");
+    return RTS_E_NOMEM;
+  }
+  P->p = *params;
+  P->N = params->n_grid; P->W = params->support; P->OS = params->oversample;
+  P->WN = P->W + 1;
+  P->WNP = (P->WN + 3) & ~3;
+  P->C = params->n_chan; P->B = params->n_base; P->T = params->n_time;
+  P->ncopy = 1 + params->conjugate;
+  P->r0 = (P->W & 1) ? -(P->OS / 2) : 0;
+  P->h_lo = (P->W & 1) ? (P->W - 1) / 2 : P->W / 2 - 1;
+  P->beta = params->beta > 0.0 ? params->beta : 2.34 * P->W;
+  P->tile = params->tile ? params->tile : choose_tile(P->N, P->WN);
+  if (P->tile == 0) {
+    set_error("no legal tile size for n_grid=%d support=%d", P->N, P->W);
+    return RTS_E_UNSUPPORTED;
+  }
+  P->nT = P->N / P->tile;
+  P->nT2 = P->nT * P->nT;
+  P->nkeys = (int64_t)P->C * P->nT2;
+  RTS_REQUIRE(P->nkeys < ((int64_t)1 << 31), "too many (channel, tile) pairs");
+  P->seg_max = choose_seg_max(P->W, P->T);
+  if (!tile_supported(P->W, P->seg_max)) {
+    set_error("support %d is not instantiated", P->W);
+    return RTS_E_UNSUPPORTED;
+  }
+  fill_tables(*P);
+  RTS_HIP(hipGetDevice(&P->device));
+  hipStream_t s = (hipStream_t)stream;
+
+  const int64_t nsamp = (int64_t)P->C * P->B * P->T;
+  P->scan_blocks = (P->nkeys + 4095) / 4096;
+  RTS_HIP(dalloc(&P->d_tabE, P->tabE.size()));
+  RTS_HIP(dalloc(&P->d_scale, (size_t)P->C));
+  RTS_HIP(dalloc(&P->d_coords, (size_t)nsamp * P->ncopy));
+  RTS_HIP(dalloc(&P->d_tile_off, (size_t)P->nkeys + 1));
+  RTS_HIP(dalloc(&P->d_cursor, (size_t)P->nkeys));
+  RTS_HIP(dalloc(&P->d_scan_tmp, (size_t)P->scan_blocks + 1));
+  RTS_HIP(dalloc(&P->d_stats, 8));
+  RTS_HIP(dalloc(&P->d_chi2_part, (size_t)P->nkeys));
+
+  std::vector<double> scale(P->C);
+  for (int c = 0; c < P->C; ++c) scale[c] = freq_hz[c] / (kCLight * params->cell_lambda);
+  RTS_HIP(hipMemcpyAsync(P->d_tabE, P->tabE.data(), P->tabE.size() * sizeof(float),
+                         hipMemcpyHostToDevice, s));
+  RTS_HIP(hipMemcpyAsync(P->d_scale, scale.data(), scale.size() * sizeof(double),
+                         hipMemcpyHostToDevice, s));
+  RTS_HIP(hipMemsetAsync(P->d_cursor, 0, (size_t)P->nkeys * sizeof(uint32_t), s));
+  RTS_HIP(hipMemsetAsync(P->d_stats, 0, 8 * sizeof(unsigned long long), s));
+
+  PlanArgs pa = plan_args(*P, uvw_m, weights);
+  RTS_HIP(launch_plan_count(pa, s));
+  RTS_HIP(launch_scan(P->d_cursor, P->d_tile_off, P->d_cursor, P->d_scan_tmp, P->nkeys, s));
+  unsigned long long stats[8] = {0};
+  uint32_t total = 0;
+  RTS_HIP(hipMemcpyAsync(stats, P->d_stats, sizeof stats, hipMemcpyDeviceToHost, s));
+  RTS_HIP(hipMemcpyAsync(&total, P->d_tile_off + P->nkeys, sizeof total, hipMemcpyDeviceToHost, s));
+  RTS_HIP(hipStreamSynchronize(s));
+  if ((int64_t)stats[4] != (int64_t)total) {
+    set_error("work-list count mismatch (%llu listed, %u scanned)", stats[4], total);
+    return RTS_E_HIP;
+  }
+  P->list_cap = std::max<int64_t>(total, 1);
+  RTS_HIP(dalloc(&P->d_list, (size_t)P->list_cap));
+  pa.list = P->d_list;
+  RTS_HIP(launch_plan_scatter(pa, s));
+
+  rts_plan_info &I = P->info;
+  I.n_samples = nsamp;
+  I.n_valid = (int64_t)stats[0];
+  I.n_flagged = (int64_t)stats[1];
+  I.n_offgrid = (int64_t)stats[2];
+  I.n_segments = (int64_t)stats[3];
+  I.n_listings = (int64_t)total;
+  I.tile = P->tile;
+  I.seg_max = P->seg_max;
+  I.workspace_bytes = (int64_t)(P->tabE.size() * 4 + P->C * 8 + nsamp * P->ncopy * 2 +
+                                (P->nkeys + 1) * 4 + P->nkeys * 4 + (P->scan_blocks + 1) * 4 + 64 +
+                                P->nkeys * 8 + P->list_cap * 8);
+  *out = P.release();
+  return RTS_OK;
+}
+
+rts_status rts_grid(rts_plan_t plan, const float *vis, const float *weights, float *grid,
+                    void *stream) {
+  if (rts_status st = check_plan(plan)) return st;
+  RTS_REQUIRE(vis && weights && grid, "vis, weights and grid must be non-NULL");
+  RTS_REQUIRE(aligned(vis, 8) && aligned(weights, 4) && aligned(grid, 16),
+              "vis must be 8-byte, weights 4-byte and grid 16-byte aligned");
+  TileArgs a = tile_args(*plan);
+  a.vis = (const float2 *)vis;
+  a.w = weights;
+  a.gout = (float2 *)grid;
+  RTS_HIP(launch_tile(kGrid, *plan, a, (hipStream_t)stream));
+  return RTS_OK;
+}
+
+rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *stream) {
+  if (rts_status st = check_plan(plan)) return st;
+  RTS_REQUIRE(grid && vis_out, "grid and vis_out must be non-NULL");
+  RTS_REQUIRE(aligned(grid, 8) && aligned(vis_out, 8), "grid and vis_out must be 8-byte aligned");
+  TileArgs a = tile_args(*plan);
+  a.gin = (const float2 *)grid;
+  a.model = (float2 *)vis_out;
+  RTS_HIP(launch_tile(kDegrid, *plan, a, (hipStream_t)stream));
+  return RTS_OK;
+}
+
+rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weights,
+                           const float *grid_in, float *model_out, float *grid_out,
+                           double *chi2_out, void *stream) {
+  if (rts_status st = check_plan(plan)) return st;
+  if (plan->ncopy != 1) {
+    set_error("rts_grid_degrid does not support plans built with conjugate=1");
+    return RTS_E_UNSUPPORTED;
+  }
+  RTS_REQUIRE(vis && weights && grid_in && grid_out, "vis, weights, grid_in, grid_out must be non-NULL");
+  RTS_REQUIRE(aligned(vis, 8) && aligned(weights, 4) && aligned(grid_in, 8) && aligned(grid_out, 16) &&
+                  aligned(model_out, 8) && aligned(chi2_out, 8),
+              "misaligned buffer");
+  const size_t gbytes = (size_t)plan->C * plan->N * plan->N * 8;
+  const char *gi = (const char *)grid_in, *go = (const char *)grid_out;
+  RTS_REQUIRE(gi + gbytes <= go || go + gbytes <= gi, "grid_in and grid_out overlap");
+  TileArgs a = tile_args(*plan);
+  a.vis = (const float2 *)vis;
+  a.w = weights;
+  a.gin = (const float2 *)grid_in;
+  a.gout = (float2 *)grid_out;
+  a.model = (float2 *)model_out;
+  a.write_model = model_out != nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  RTS_HIP(launch_tile(kFused, *plan, a, s));
+  if (chi2_out) RTS_HIP(launch_chi2_reduce(plan->d_chi2_part, plan->nkeys, chi2_out, s));
+  return RTS_OK;
+}
+
+rts_status rts_compute_coords(const rts_params *params, const double *uvw_m, const double *freq_hz,
+                              const float *weights, int32_t *out, void *stream) {
+  if (rts_status st = validate(params)) return st;
+  RTS_REQUIRE(uvw_m && freq_hz && weights && out, "null pointer argument");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> scale(params->n_chan);
+  for (int c = 0; c < params->n_chan; ++c) scale[c] = freq_hz[c] / (kCLight * params->cell_lambda);
+  double *d_scale = nullptr;
+  RTS_HIP(dalloc(&d_scale, scale.size()));
+  hipError_t e = hipMemcpyAsync(d_scale, scale.data(), scale.size() * sizeof(double),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_coords(uvw_m, d_scale, weights, out, params->n_grid, params->support,
+                      params->oversample, params->n_chan, params->n_base, params->n_time, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(d_scale);
+  RTS_HIP(e);
+  return RTS_OK;
+}
+
+rts_status rts_plan_get_table(rts_plan_t plan, float *tab, int64_t capacity) {
+  if (rts_status st = check_plan(plan)) return st;
+  RTS_REQUIRE(tab != nullptr, "tab is NULL");
+  RTS_REQUIRE(capacity >= (int64_t)plan->tab.size(), "capacity %lld < %zu", (long long)capacity,
+              plan->tab.size());
+  std::memcpy(tab, plan->tab.data(), plan->tab.size() * sizeof(float));
+  return RTS_OK;
+}
+
+rts_status rts_plan_get_info(rts_plan_t plan, rts_plan_info *info) {
+  if (rts_status st = check_plan(plan)) return st;
+  RTS_REQUIRE(info != nullptr, "info is NULL");
+  *info = plan->info;
+  return RTS_OK;
+}
+
+rts_status rts_plan_destroy(rts_plan_t plan) {
+  if (!plan) return RTS_OK;
+  hipError_t e = hipDeviceSynchronize();
+  free_plan(plan);
+  RTS_HIP(e);
+  return RTS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Internal declarations shared by the host ABI and the HIP kernels of librtsgrid.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rtsgrid.h"
+
+namespace rts {
+
+constexpr int kMaxW = 16;
+constexpr int kMaxOS = 64;
+constexpr int kMaxN = 8192;
+constexpr int kMaxTile = 128;
+constexpr double kCLight = 299792458.0;
+constexpr int kBlock = 256;          // threads per workgroup of every kernel here
+
+enum Mode { kGrid = 0, kDegrid = 1, kFused = 2 };
+
+// Work-list record (8 bytes) for one (segment, tile) pair.
+//   x: index of the segment's first sample in the [C][B][T] visibility arrays
+//   y: X0 | Y0 << 13 | (nt-1) << 26 | home << 29 | copy << 30 | any_valid << 31
+// (X0, Y0) is the origin cell of the segment's (W+1)x(W+1) window, nt its sample
+// count, home marks the listing in the tile that holds the window origin (the one
+// that writes the model), copy marks the conjugate (-u,-v) copy.
+constexpr uint32_t kRecXMask = 0x1FFFu;
+constexpr int kRecYShift = 13;
+constexpr int kRecNtShift = 26;
+constexpr int kRecHomeBit = 29;
+constexpr int kRecCopyBit = 30;
+constexpr int kRecAnyBit = 31;
+
+// Per-sample packed window coordinates (16 bits):
+//   bit 15 valid | sy << 7 | sx, with s = d*OS + (r - r0) in [0, 2*OS): d in {0,1} is
+//   the sample's cell offset from the window origin + h_lo, r its kernel phase.
+constexpr uint16_t kCoordValid = 0x8000u;
+
+struct PlanArgs {
+  const double *uvw;      // [B][T][3]
+  const double *scale;    // [C]  f_c / (c du)
+  const float *w;         // [C][B][T]
+  uint16_t *coords;       // [C][ncopy][B][T]
+  uint2 *list;            // [capacity]
+  uint32_t *counts;       // [nkeys] counts (count pass) / cursors (scatter pass)
+  unsigned long long *stats;  // [5]: valid, flagged, offgrid, segments, listings
+  int N, W, OS, WN, r0, h_lo;
+  int tile, nT, nT2;
+  int C, B, T, ncopy, seg_max;
+  int cg, use_lds;
+};
+
+struct TileArgs {
+  const uint2 *list;
+  const uint32_t *tile_off;  // [nkeys+1]
+  const uint16_t *coords;
+  const float *tabE;         // [2*OS][WNP]
+  const float2 *vis;
+  const float *w;
+  const float2 *gin;
+  float2 *model;
+  float2 *gout;
+  double *chi2_part;         // [nkeys]
+  int N, tile, nT, nT2, nkeys;
+  int B, T, ncopy;
+  int OS2, WNP;
+  int write_model;
+};
+
+}  // namespace rts
+
+// Plan state behind the opaque rts_plan_t handle.
+struct rts_plan_s {
+  rts_params p{};
+  int N = 0, W = 0, OS = 0, WN = 0, WNP = 0, tile = 0, nT = 0, nT2 = 0;
+  int C = 0, B = 0, T = 0, ncopy = 1, r0 = 0, h_lo = 0, seg_max = 0;
+  double beta = 0.0;
+  int64_t nkeys = 0;
+  int device = 0;
+  std::vector<float> tab;    // [OS][W]
+  std::vector<float> tabE;   // [2*OS][WNP]
+  float *d_tabE = nullptr;
+  double *d_scale = nullptr;
+  uint16_t *d_coords = nullptr;
+  uint2 *d_list = nullptr;
+  uint32_t *d_tile_off = nullptr;
+  uint32_t *d_cursor = nullptr;
+  uint32_t *d_scan_tmp = nullptr;
+  unsigned long long *d_stats = nullptr;
+  double *d_chi2_part = nullptr;
+  int64_t list_cap = 0;
+  int64_t scan_blocks = 0;
+  rts_plan_info info{};
+};
+
+namespace rts {
+
+using Plan = ::rts_plan_s;
+
+// error state (abi.cpp)
+void set_error(const char *fmt, ...);
+
+// kernel launchers (plan.hip)
+hipError_t launch_plan_count(const PlanArgs &a, hipStream_t s);
+hipError_t launch_plan_scatter(const PlanArgs &a, hipStream_t s);
+hipError_t launch_scan(const uint32_t *counts, uint32_t *tile_off, uint32_t *cursor,
+                       uint32_t *tmp, int64_t n, hipStream_t s);
+hipError_t launch_coords(const double *uvw, const double *scale, const float *w, int32_t *out,
+                         int N, int W, int OS, int C, int B, int T, hipStream_t s);
+hipError_t launch_chi2_reduce(const double *part, int64_t n, double *out, hipStream_t s);
+
+// tile kernels (tile_*.hip)
+template <int MODE>
+hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s);
+hipError_t launch_tile(int mode, const Plan &P, const TileArgs &a, hipStream_t s);
+bool tile_supported(int W, int seg_max);
+
+}  // namespace rts

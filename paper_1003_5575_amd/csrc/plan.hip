@@ -1,0 +1,407 @@
+// Plan kernels: FP64 uv -> grid coordinates, segmentation of each baseline's
+// track, and the counting sort of (segment, tile) listings by (channel, tile).
+//
+// Section 5.2 of the paper bins visibilities by uv bin and sorts them so that a
+// workgroup reads only the visibilities near its pixels.  Here the sort key is the
+// owning (channel, tile) of every tile a segment's window touches, and the sort is
+// a counting sort (histogram -> exclusive scan -> scatter), O(v) instead of the
+// O(v log v) comparison sort the paper used.
+#include "internal.h"
+
+namespace rts {
+namespace {
+
+// x = u*s + N/2 and xs = floor(x*OS + 1/2), each step rounded once (no FMA
+// contraction), so that the result is bit-identical to a plain IEEE evaluation.
+__device__ __forceinline__ bool snap(double u, double v, double s, int N, int OS, int &xs,
+                                     int &ys) {
+  const double half = (double)(N / 2);
+  const double x = __dadd_rn(__dmul_rn(u, s), half);
+  const double y = __dadd_rn(__dmul_rn(v, s), half);
+  const double xo = floor(__dadd_rn(__dmul_rn(x, (double)OS), 0.5));
+  const double yo = floor(__dadd_rn(__dmul_rn(y, (double)OS), 0.5));
+  if (!(fabs(xo) < 1073741824.0) || !(fabs(yo) < 1073741824.0)) {  // false for NaN too
+    xs = ys = 0;
+    return false;
+  }
+  xs = (int)xo;
+  ys = (int)yo;
+  return true;
+}
+
+// Split an oversampled coordinate into cell and phase r in [r0, r0 + OS).
+__device__ __forceinline__ void split(int xs, int r0, int OS, int &cell, int &r) {
+  const int q = xs - r0;
+  cell = (q >= 0) ? q / OS : -((-q + OS - 1) / OS);
+  r = xs - cell * OS;
+}
+
+struct Sample {
+  int cx, cy, rx, ry;
+  bool valid;
+  bool flagged;
+};
+
+__device__ __forceinline__ Sample sample(const PlanArgs &a, double u, double v, double s,
+                                         float w) {
+  Sample o;
+  int xs, ys;
+  const bool fin = snap(u, v, s, a.N, a.OS, xs, ys);
+  split(xs, a.r0, a.OS, o.cx, o.rx);
+  split(ys, a.r0, a.OS, o.cy, o.ry);
+  const bool on = fin && o.cx - a.h_lo >= 0 && o.cx - a.h_lo + a.W - 1 <= a.N - 1 &&
+                  o.cy - a.h_lo >= 0 && o.cy - a.h_lo + a.W - 1 <= a.N - 1;
+  o.flagged = (w == 0.0f);
+  o.valid = on && !o.flagged;
+  return o;
+}
+
+struct Seg {
+  int t0, nt;
+  bool any;
+  int X0, Y0;
+};
+
+// Walk one baseline track of channel c and emit its segments in time order.  A
+// segment is a run of at most seg_max consecutive samples whose valid samples'
+// cells span at most 2x2 cells, so a (W+1)x(W+1) window holds all their taps.
+// Segments partition the track: invalid samples ride along (or form a segment
+// with any == false), so every sample belongs to exactly one segment.
+template <class F>
+__device__ __forceinline__ void walk_track(const PlanArgs &a, int c, int b, int copy, F &&emit) {
+  const double s = a.scale[c];
+  const double sg = copy ? -1.0 : 1.0;
+  const double *uv = a.uvw + (size_t)b * a.T * 3;
+  const float *w = a.w + ((size_t)c * a.B + b) * a.T;
+  int t0 = 0;
+  bool any = false;
+  int mnx = 0, mxx = 0, mny = 0, mxy = 0;
+  auto close = [&](int t1) {
+    Seg sgm;
+    sgm.t0 = t0;
+    sgm.nt = t1 - t0;
+    sgm.any = any;
+    sgm.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
+    sgm.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+    emit(sgm);
+  };
+  for (int t = 0; t < a.T; ++t) {
+    const Sample sm = sample(a, sg * uv[t * 3], sg * uv[t * 3 + 1], s, w[t]);
+    if (sm.valid) {
+      if (any) {
+        const int nx0 = min(mnx, sm.cx), nx1 = max(mxx, sm.cx);
+        const int ny0 = min(mny, sm.cy), ny1 = max(mxy, sm.cy);
+        if (nx1 - nx0 > 1 || ny1 - ny0 > 1 || t - t0 >= a.seg_max) {
+          close(t);
+          t0 = t;
+          mnx = mxx = sm.cx;
+          mny = mxy = sm.cy;
+        } else {
+          mnx = nx0; mxx = nx1; mny = ny0; mxy = ny1;
+        }
+      } else {
+        if (t - t0 >= a.seg_max) {
+          close(t);
+          t0 = t;
+        }
+        any = true;
+        mnx = mxx = sm.cx;
+        mny = mxy = sm.cy;
+      }
+    } else if (t - t0 >= a.seg_max) {
+      close(t);
+      t0 = t;
+      any = false;
+    }
+  }
+  close(a.T);
+}
+
+// Listings of a segment: every tile its window overlaps (at most 2 per axis since
+// tile >= W+1).  A segment without valid samples of the +uv copy is listed once,
+// in tile (0,0), so that its home listing writes its zero model.
+template <class G>
+__device__ __forceinline__ void for_listings(const PlanArgs &a, int c, int copy, const Seg &sg,
+                                             G &&fn) {
+  if (!sg.any) {
+    if (copy == 0) fn((int64_t)c * a.nT2, 0, 0, true);
+    return;
+  }
+  const int tx0 = sg.X0 / a.tile, tx1 = (sg.X0 + a.WN - 1) / a.tile;
+  const int ty0 = sg.Y0 / a.tile, ty1 = (sg.Y0 + a.WN - 1) / a.tile;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx)
+      fn((int64_t)c * a.nT2 + ty * a.nT + tx, tx, ty, tx == tx0 && ty == ty0);
+}
+
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v) {
+  __shared__ unsigned long long red[kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kBlock / 64; ++i) t += red[i];
+  return t;
+}
+
+// Pass 1: packed per-sample coordinates, sample statistics and listing counts.
+__global__ __launch_bounds__(kBlock) void k_plan_count(PlanArgs a) {
+  extern __shared__ uint32_t hist[];
+  const int c0 = blockIdx.y * a.cg;
+  const int c1 = min(a.C, c0 + a.cg);
+  const int nloc = (c1 - c0) * a.nT2;
+  if (a.use_lds) {
+    for (int i = threadIdx.x; i < nloc; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+  }
+  unsigned long long nvalid = 0, nflag = 0, noff = 0, nseg = 0, nlist = 0;
+  const int b2 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b2 < a.B * a.ncopy) {
+    const int copy = b2 / a.B, b = b2 - copy * a.B;
+    const double sg = copy ? -1.0 : 1.0;
+    const double *uv = a.uvw + (size_t)b * a.T * 3;
+    for (int c = c0; c < c1; ++c) {
+      const double s = a.scale[c];
+      const float *w = a.w + ((size_t)c * a.B + b) * a.T;
+      uint16_t *co = a.coords + (((size_t)c * a.ncopy + copy) * a.B + b) * a.T;
+      walk_track(a, c, b, copy, [&](const Seg &sgm) {
+        ++nseg;
+        for (int t = sgm.t0; t < sgm.t0 + sgm.nt; ++t) {
+          const Sample sm = sample(a, sg * uv[t * 3], sg * uv[t * 3 + 1], s, w[t]);
+          uint16_t code = 0;
+          if (sm.valid) {
+            const int dx = sm.cx - (sgm.X0 + a.h_lo), dy = sm.cy - (sgm.Y0 + a.h_lo);
+            const int sx = dx * a.OS + (sm.rx - a.r0), sy = dy * a.OS + (sm.ry - a.r0);
+            code = (uint16_t)(kCoordValid | (sy << 7) | sx);
+          }
+          co[t] = code;
+          if (copy == 0) {
+            nvalid += sm.valid;
+            nflag += sm.flagged;
+            noff += !sm.valid && !sm.flagged;
+          }
+        }
+        for_listings(a, c, copy, sgm, [&](int64_t key, int, int, bool) {
+          ++nlist;
+          if (a.use_lds)
+            atomicAdd(&hist[key - (int64_t)c0 * a.nT2], 1u);
+          else
+            atomicAdd(&a.counts[key], 1u);
+        });
+      });
+    }
+  }
+  if (a.use_lds) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nloc; i += blockDim.x)
+      if (hist[i]) atomicAdd(&a.counts[(int64_t)c0 * a.nT2 + i], hist[i]);
+  }
+  const unsigned long long v0 = block_sum_u64(nvalid);
+  const unsigned long long v1 = block_sum_u64(nflag);
+  const unsigned long long v2 = block_sum_u64(noff);
+  const unsigned long long v3 = block_sum_u64(nseg);
+  const unsigned long long v4 = block_sum_u64(nlist);
+  if (threadIdx.x == 0) {
+    if (v0) atomicAdd(&a.stats[0], v0);
+    if (v1) atomicAdd(&a.stats[1], v1);
+    if (v2) atomicAdd(&a.stats[2], v2);
+    if (v3) atomicAdd(&a.stats[3], v3);
+    if (v4) atomicAdd(&a.stats[4], v4);
+  }
+}
+
+__device__ __forceinline__ uint2 make_rec(const PlanArgs &a, int c, int b, int copy,
+                                          const Seg &sg, bool home) {
+  uint2 r;
+  r.x = (uint32_t)((((size_t)c * a.B + b) * a.T) + sg.t0);
+  r.y = (uint32_t)sg.X0 | ((uint32_t)sg.Y0 << kRecYShift) | ((uint32_t)(sg.nt - 1) << kRecNtShift) |
+        ((uint32_t)home << kRecHomeBit) | ((uint32_t)copy << kRecCopyBit) |
+        ((uint32_t)sg.any << kRecAnyBit);
+  return r;
+}
+
+// Pass 2: every listing claims its slot.  With the LDS histogram, a workgroup
+// reserves one contiguous range per key with a single global atomic and hands
+// out slots from LDS.
+__global__ __launch_bounds__(kBlock) void k_plan_scatter(PlanArgs a) {
+  extern __shared__ uint32_t base[];
+  const int c0 = blockIdx.y * a.cg;
+  const int c1 = min(a.C, c0 + a.cg);
+  const int nloc = (c1 - c0) * a.nT2;
+  const int b2 = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = b2 < a.B * a.ncopy;
+  const int copy = active ? b2 / a.B : 0, b = active ? b2 - copy * a.B : 0;
+  if (a.use_lds) {
+    for (int i = threadIdx.x; i < nloc; i += blockDim.x) base[i] = 0;
+    __syncthreads();
+    if (active)
+      for (int c = c0; c < c1; ++c)
+        walk_track(a, c, b, copy, [&](const Seg &sgm) {
+          for_listings(a, c, copy, sgm, [&](int64_t key, int, int, bool) {
+            atomicAdd(&base[key - (int64_t)c0 * a.nT2], 1u);
+          });
+        });
+    __syncthreads();
+    for (int i = threadIdx.x; i < nloc; i += blockDim.x)
+      if (base[i]) base[i] = atomicAdd(&a.counts[(int64_t)c0 * a.nT2 + i], base[i]);
+    __syncthreads();
+  }
+  if (!active) return;
+  for (int c = c0; c < c1; ++c)
+    walk_track(a, c, b, copy, [&](const Seg &sgm) {
+      for_listings(a, c, copy, sgm, [&](int64_t key, int, int, bool home) {
+        const uint32_t pos = a.use_lds ? atomicAdd(&base[key - (int64_t)c0 * a.nT2], 1u)
+                                       : atomicAdd(&a.counts[key], 1u);
+        a.list[pos] = make_rec(a, c, b, copy, sgm, home);
+      });
+    });
+}
+
+// ---------------------------------------------------------------- exclusive scan
+constexpr int kScanPerThread = 16;
+constexpr int kScanPerBlock = kBlock * kScanPerThread;
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total) {
+  __shared__ uint32_t ws[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t n = __shfl_up(x, o, 64);
+    if (lane >= o) x += n;
+  }
+  __syncthreads();
+  if (lane == 63) ws[wid] = x;
+  __syncthreads();
+  uint32_t pre = 0;
+  total = 0;
+  for (int i = 0; i < kBlock / 64; ++i) {
+    if (i < wid) pre += ws[i];
+    total += ws[i];
+  }
+  return pre + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_local(const uint32_t *in, uint32_t *out,
+                                                       uint32_t *bsum, int64_t n) {
+  const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + (int64_t)threadIdx.x * kScanPerThread;
+  uint32_t v[kScanPerThread];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanPerThread; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t total;
+  uint32_t pre = block_excl_scan(s, total);
+#pragma unroll
+  for (int i = 0; i < kScanPerThread; ++i) {
+    if (base + i < n) out[base + i] = pre;
+    pre += v[i];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the block sums in place; bsum[nb] = total.
+__global__ __launch_bounds__(kBlock) void k_scan_bsum(uint32_t *bsum, int64_t nb) {
+  uint32_t carry = 0;
+  for (int64_t start = 0; start < nb; start += kBlock) {
+    const int64_t i = start + threadIdx.x;
+    const uint32_t v = (i < nb) ? bsum[i] : 0u;
+    uint32_t total;
+    const uint32_t pre = block_excl_scan(v, total);
+    if (i < nb) bsum[i] = carry + pre;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *tile_off, uint32_t *cursor,
+                                                     const uint32_t *bsum, int64_t n, int64_t nb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const uint32_t v = tile_off[i] + bsum[i / kScanPerBlock];
+    tile_off[i] = v;
+    cursor[i] = v;
+  }
+  if (i == 0) tile_off[n] = bsum[nb];
+}
+
+// ------------------------------------------------------------ coordinates (a1)
+__global__ __launch_bounds__(kBlock) void k_coords(const double *uvw, const double *scale,
+                                                   const float *w, int32_t *out, int N, int W,
+                                                   int OS, int C, int B, int T) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)C * B * T;
+  if (i >= n) return;
+  const int64_t bt = i % ((int64_t)B * T);
+  const int c = (int)(i / ((int64_t)B * T));
+  PlanArgs a{};
+  a.N = N; a.W = W; a.OS = OS;
+  a.r0 = (W & 1) ? -(OS / 2) : 0;
+  a.h_lo = (W & 1) ? (W - 1) / 2 : W / 2 - 1;
+  int xs, ys;
+  const bool fin = snap(uvw[bt * 3], uvw[bt * 3 + 1], scale[c], N, OS, xs, ys);
+  const Sample sm = sample(a, uvw[bt * 3], uvw[bt * 3 + 1], scale[c], w[i]);
+  out[i * 3] = fin ? xs : 0;
+  out[i * 3 + 1] = fin ? ys : 0;
+  out[i * 3 + 2] = sm.valid ? 1 : 0;
+}
+
+__global__ __launch_bounds__(1024) void k_chi2_reduce(const double *part, int64_t n, double *out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    *out = t;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_plan_count(const PlanArgs &a, hipStream_t s) {
+  dim3 grid((a.B * a.ncopy + kBlock - 1) / kBlock, (a.C + a.cg - 1) / a.cg);
+  const size_t lds = a.use_lds ? (size_t)a.cg * a.nT2 * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL(k_plan_count, grid, dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_scatter(const PlanArgs &a, hipStream_t s) {
+  dim3 grid((a.B * a.ncopy + kBlock - 1) / kBlock, (a.C + a.cg - 1) / a.cg);
+  const size_t lds = a.use_lds ? (size_t)a.cg * a.nT2 * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL(k_plan_scatter, grid, dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t *counts, uint32_t *tile_off, uint32_t *cursor,
+                       uint32_t *tmp, int64_t n, hipStream_t s) {
+  const int64_t nb = (n + kScanPerBlock - 1) / kScanPerBlock;
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kBlock), 0, s, counts, tile_off, tmp, n);
+  hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kBlock), 0, s, tmp, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     tile_off, cursor, (const uint32_t *)tmp, n, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_coords(const double *uvw, const double *scale, const float *w, int32_t *out,
+                         int N, int W, int OS, int C, int B, int T, hipStream_t s) {
+  const int64_t n = (int64_t)C * B * T;
+  hipLaunchKernelGGL(k_coords, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, uvw,
+                     scale, w, out, N, W, OS, C, B, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_chi2_reduce(const double *part, int64_t n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_chi2_reduce, dim3(1), dim3(1024), 0, s, part, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace rts

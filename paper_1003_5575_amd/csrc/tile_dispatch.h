@@ -1,0 +1,43 @@
+// Instantiation of the tile kernel for every supported (W+1, samples-per-segment)
+// pair of one mode.  Included once per mode so the three modes compile in parallel.
+#pragma once
+
+#include "tile_kernel.h"
+
+namespace rts {
+
+#define RTS_TILE_CASE(WNV, SM)                                                               \
+  case (WNV)*16 + (SM): {                                                                    \
+    if (lds > 65536) {                                                                       \
+      hipError_t e = hipFuncSetAttribute((const void *)k_tile<WNV, SM, MODE>,                \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      if (e != hipSuccess) return e;                                                         \
+    }                                                                                        \
+    hipLaunchKernelGGL((k_tile<WNV, SM, MODE>), dim3(nblk), dim3(kBlock), lds, s, a);       \
+    break;                                                                                   \
+  }
+
+template <int MODE>
+hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s) {
+  const unsigned nblk = (unsigned)P.nkeys;
+  size_t lds = (size_t)a.OS2 * a.WNP * sizeof(float);
+  if (MODE != kDegrid) lds += (size_t)2 * P.tile * P.tile * sizeof(float);
+  switch (P.WN * 16 + P.seg_max) {
+    RTS_TILE_CASE(3, 4) RTS_TILE_CASE(3, 8)
+    RTS_TILE_CASE(4, 4) RTS_TILE_CASE(4, 8)
+    RTS_TILE_CASE(5, 4) RTS_TILE_CASE(5, 8)
+    RTS_TILE_CASE(6, 4) RTS_TILE_CASE(6, 8)
+    RTS_TILE_CASE(7, 4) RTS_TILE_CASE(7, 8)
+    RTS_TILE_CASE(8, 4) RTS_TILE_CASE(8, 8)
+    RTS_TILE_CASE(9, 4) RTS_TILE_CASE(9, 8)
+    RTS_TILE_CASE(10, 4) RTS_TILE_CASE(11, 4) RTS_TILE_CASE(12, 4) RTS_TILE_CASE(13, 4)
+    RTS_TILE_CASE(14, 2) RTS_TILE_CASE(15, 2) RTS_TILE_CASE(16, 2) RTS_TILE_CASE(17, 2)
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#undef RTS_TILE_CASE
+
+}  // namespace rts
