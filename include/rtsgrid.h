@@ -70,7 +70,7 @@ typedef struct {
   double cell_lambda;   /* du > 0: uv cell size in wavelengths                           */
   double beta;          /* Kaiser-Bessel shape; <= 0 selects 2.34 * W                     */
   int32_t conjugate;    /* 1: also grid conj(w V) at (-u, -v) (rts_grid only)             */
-  int32_t tile;         /* uv tile edge in cells: divides N, >= W+1, <= 128; 0 = choose   */
+  int32_t tile;         /* uv tile edge in cells: even, divides N, >= W+1, <= 64; 0 = choose */
   int32_t precision;    /* rts_precision                                                 */
   int32_t reserved;     /* must be 0                                                     */
 } rts_params;
@@ -82,6 +82,8 @@ typedef struct {
   int64_t n_offgrid;    /* samples with w != 0 but a tap off the grid (or non-finite uvw) */
   int64_t n_segments;   /* runs of one baseline's samples sharing a (W+1)^2 cell window   */
   int64_t n_listings;   /* (segment, tile) pairs in the work list                        */
+  int64_t n_dropped;    /* listings beyond the work-list capacity after rts_plan_update
+                           (non-zero: results are incomplete, build a new plan)          */
   int64_t workspace_bytes;
   int32_t tile;         /* tile edge chosen                                               */
   int32_t seg_max;      /* most samples per segment                                       */
@@ -97,6 +99,15 @@ typedef struct {
  */
 rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double *uvw_m,
                          const double *freq_hz, const float *weights, void *stream);
+
+/* Re-plan in place for a new cadence with the same shape (new uvw and weights):
+ * recomputes coordinates, segments and the tile-sorted work list into the plan's
+ * existing workspace.  Allocates nothing and does not synchronise, so a whole
+ * cadence (update, then grid/degrid calls) can be enqueued back to back.  The
+ * work list keeps the capacity sized at rts_grid_plan (+1/8 headroom); listings
+ * beyond it are dropped and counted in rts_plan_info.n_dropped, which
+ * rts_plan_get_info reports (synchronising the device). */
+rts_status rts_plan_update(rts_plan_t plan, const double *uvw_m, const float *weights, void *stream);
 
 /* Eq. (1): grid[c] = sum_i w_i V_i k k over valid samples (and conj(w V) at -uv
  * when the plan was built with conjugate=1).  `grid` [C][N][N] is overwritten. */

@@ -116,6 +116,14 @@ class GridPlan:
                    "rts_plan_get_table")
         return buf.reshape(self.params.oversample, self.params.support)
 
+    def update(self, uvw, weights, stream=None):
+        """Re-plan in place for new uvw / weights of the same shape (asynchronous)."""
+        torch = _torch()
+        _check_dev(uvw, "uvw", torch.float64, (self.B, self.T, 3))
+        _check_dev(weights, "weights", torch.float32, (self.C, self.B, self.T))
+        _lib.check(_lib.load().rts_plan_update(self.handle, _ptr(uvw), _ptr(weights), _stream(stream)),
+                   "rts_plan_update")
+
     # -------------------------------------------------------------- operations
     def _vis_shape(self):
         return (self.C, self.B, self.T)

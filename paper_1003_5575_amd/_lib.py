@@ -15,7 +15,7 @@ RTS_OK, RTS_E_INVALID, RTS_E_NOMEM, RTS_E_HIP, RTS_E_UNSUPPORTED = range(5)
 STATUS_NAMES = {0: "RTS_OK", 1: "RTS_E_INVALID", 2: "RTS_E_NOMEM", 3: "RTS_E_HIP", 4: "RTS_E_UNSUPPORTED"}
 
 EXPORTED = (
-    "rts_grid_plan", "rts_grid", "rts_degrid", "rts_grid_degrid", "rts_compute_coords",
+    "rts_grid_plan", "rts_plan_update", "rts_grid", "rts_degrid", "rts_grid_degrid", "rts_compute_coords",
     "rts_plan_get_table", "rts_plan_get_info", "rts_plan_destroy", "rts_last_error", "rts_version",
 )
 
@@ -34,6 +34,7 @@ class RtsPlanInfo(ctypes.Structure):
     _fields_ = [
         ("n_samples", ctypes.c_int64), ("n_valid", ctypes.c_int64), ("n_flagged", ctypes.c_int64),
         ("n_offgrid", ctypes.c_int64), ("n_segments", ctypes.c_int64), ("n_listings", ctypes.c_int64),
+        ("n_dropped", ctypes.c_int64),
         ("workspace_bytes", ctypes.c_int64), ("tile", ctypes.c_int32), ("seg_max", ctypes.c_int32),
     ]
 
@@ -58,6 +59,7 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     lib.rts_grid_plan.argtypes = [ctypes.POINTER(P), ctypes.POINTER(RtsParams), P, P, P, P]
+    lib.rts_plan_update.argtypes = [P, P, P, P]
     lib.rts_grid.argtypes = [P, P, P, P, P]
     lib.rts_degrid.argtypes = [P, P, P, P]
     lib.rts_grid_degrid.argtypes = [P, P, P, P, P, P, P, P]
@@ -65,7 +67,7 @@ def load() -> ctypes.CDLL:
     lib.rts_plan_get_table.argtypes = [P, P, I64]
     lib.rts_plan_get_info.argtypes = [P, ctypes.POINTER(RtsPlanInfo)]
     lib.rts_plan_destroy.argtypes = [P]
-    for name in ("rts_grid_plan", "rts_grid", "rts_degrid", "rts_grid_degrid", "rts_compute_coords",
+    for name in ("rts_grid_plan", "rts_plan_update", "rts_grid", "rts_degrid", "rts_grid_degrid", "rts_compute_coords",
                  "rts_plan_get_table", "rts_plan_get_info", "rts_plan_destroy"):
         getattr(lib, name).restype = I
     lib.rts_last_error.restype = ctypes.c_char_p

@@ -92,8 +92,8 @@ rts_status validate(const rts_params *p) {
 
 int choose_tile(int N, int WN) {
   // 64 balances window duplication across tile edges ((64+W)^2/64^2) against LDS
-  // per workgroup (32 KiB of complex FP32); fall back to the nearest legal size.
-  const int prefs[] = {64, 128, 32, 16};
+  // per workgroup (64 KiB of complex FP64); fall back to the nearest legal size.
+  const int prefs[] = {64, 32, 16};
   for (int t : prefs)
     if (t >= WN && N % t == 0) return t;
   for (int t = kMaxTile; t >= WN; t -= 2)
@@ -136,9 +136,45 @@ void free_plan(Plan *P) {
   hipFree(P->d_tile_off);
   hipFree(P->d_cursor);
   hipFree(P->d_scan_tmp);
+  hipFree(P->d_hist);
+  hipFree(P->d_offs);
   hipFree(P->d_stats);
   hipFree(P->d_chi2_part);
   delete P;
+}
+
+// Channels per workgroup of the chunked sort: its LDS histogram holds cg * nT2
+// counters (at most 8192, 32 KiB).
+int chunk_channels(int nT2) { return std::max(1, std::min(8, 8192 / nT2)); }
+
+// Choose the chunked counting sort when the tracks are short enough for the lane
+// path and one channel's tiles fit the LDS histogram; the (key, chunk) count
+// matrix is kept near 4M entries.
+void choose_sort(Plan &P) {
+  P.nbx = 0;
+  P.chunk = 0;
+  P.cg = 1;
+  if (P.T > 64 || P.nT2 > 8192) return;
+  int g = 1;
+  while (g < P.T) g <<= 1;
+  const int64_t per_iter = kBlock / g;
+  const int64_t ntr = (int64_t)P.ncopy * P.B;
+  const int64_t max_nbx = std::max<int64_t>(1, (ntr + per_iter - 1) / per_iter);
+  const int64_t cap_nbx = std::max<int64_t>(1, (8 << 20) / P.nkeys);
+  // The most channels per workgroup (uvw reuse) that still gives >= 1024 workgroups.
+  int64_t nbx = 1;
+  for (int cg = chunk_channels(P.nT2); cg >= 1; cg /= 2) {
+    const int64_t groups = (P.C + cg - 1) / cg;
+    nbx = std::min(max_nbx, cap_nbx);
+    P.cg = cg;
+    if (groups * nbx >= 1024) break;
+  }
+  nbx = std::max<int64_t>(nbx, 1);
+  int64_t chunk = (ntr + nbx - 1) / nbx;
+  chunk = (chunk + per_iter - 1) / per_iter * per_iter;
+  nbx = (ntr + chunk - 1) / chunk;
+  P.nbx = (int)nbx;
+  P.chunk = chunk;
 }
 
 PlanArgs plan_args(const Plan &P, const double *uvw, const float *w) {
@@ -150,11 +186,30 @@ PlanArgs plan_args(const Plan &P, const double *uvw, const float *w) {
   a.list = P.d_list;
   a.counts = P.d_cursor;
   a.stats = P.d_stats;
+  a.list_cap = P.list_cap;
   a.N = P.N; a.W = P.W; a.OS = P.OS; a.WN = P.WN; a.r0 = P.r0; a.h_lo = P.h_lo;
   a.tile = P.tile; a.nT = P.nT; a.nT2 = P.nT2;
   a.C = P.C; a.B = P.B; a.T = P.T; a.ncopy = P.ncopy; a.seg_max = P.seg_max;
-  // LDS histogram over the channels of a workgroup when it fits in 32 KiB
-  if (P.nT2 <= 8192) {
+  // Tracks of up to 64 samples: one lane per sample, channels in groups of 8 so
+  // that each lane's uvw is loaded once per group.
+  a.tgroup = 0;
+  if (P.T <= 64) {
+    int g = 1;
+    while (g < P.T) g <<= 1;
+    a.tgroup = g;
+  }
+  // per-track path: LDS histogram over the channels of a workgroup when it fits in 32 KiB
+  a.nbx = P.nbx;
+  a.chunk = P.chunk;
+  a.hist = P.d_hist;
+  a.offs = P.d_offs;
+  if (P.nbx > 0) {
+    a.use_lds = 0;
+    a.cg = P.cg;
+  } else if (a.tgroup > 0) {
+    a.use_lds = 0;
+    a.cg = 8;
+  } else if (P.nT2 <= 8192) {
     a.use_lds = 1;
     a.cg = std::max(1, std::min(8, 8192 / P.nT2));
   } else {
@@ -164,6 +219,18 @@ PlanArgs plan_args(const Plan &P, const double *uvw, const float *w) {
   return a;
 }
 
+// Exclusive scan of the listing counts into tile offsets (and cursors or
+// per-chunk offsets for the scatter pass).
+hipError_t scan_counts(const Plan &P, hipStream_t s) {
+  if (P.nbx > 0) {
+    const int64_t n = P.nkeys * P.nbx;
+    hipError_t e = launch_scan(P.d_hist, P.d_offs, nullptr, P.d_scan_tmp, n, s);
+    if (e != hipSuccess) return e;
+    return launch_tile_offsets(P.d_offs, P.nbx, P.nkeys, P.d_tile_off, s);
+  }
+  return launch_scan(P.d_cursor, P.d_tile_off, P.d_cursor, P.d_scan_tmp, P.nkeys, s);
+}
+
 TileArgs tile_args(const Plan &P) {
   TileArgs a{};
   a.list = P.d_list;
@@ -171,6 +238,7 @@ TileArgs tile_args(const Plan &P) {
   a.coords = P.d_coords;
   a.tabE = P.d_tabE;
   a.chi2_part = P.d_chi2_part;
+  a.list_cap = P.list_cap;
   a.N = P.N; a.tile = P.tile; a.nT = P.nT; a.nT2 = P.nT2; a.nkeys = (int)P.nkeys;
   a.B = P.B; a.T = P.T; a.ncopy = P.ncopy;
   a.OS2 = 2 * P.OS; a.WNP = P.WNP;
@@ -258,7 +326,9 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   hipStream_t s = (hipStream_t)stream;
 
   const int64_t nsamp = (int64_t)P->C * P->B * P->T;
-  P->scan_blocks = (P->nkeys + 4095) / 4096;
+  choose_sort(*P);
+  const int64_t nscan = P->nbx > 0 ? P->nkeys * P->nbx : P->nkeys;
+  P->scan_blocks = (nscan + 4095) / 4096;
   RTS_HIP(dalloc(&P->d_tabE, P->tabE.size()));
   RTS_HIP(dalloc(&P->d_scale, (size_t)P->C));
   RTS_HIP(dalloc(&P->d_coords, (size_t)nsamp * P->ncopy));
@@ -267,6 +337,10 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   RTS_HIP(dalloc(&P->d_scan_tmp, (size_t)P->scan_blocks + 1));
   RTS_HIP(dalloc(&P->d_stats, 8));
   RTS_HIP(dalloc(&P->d_chi2_part, (size_t)P->nkeys));
+  if (P->nbx > 0) {
+    RTS_HIP(dalloc(&P->d_hist, (size_t)nscan));
+    RTS_HIP(dalloc(&P->d_offs, (size_t)nscan + 1));
+  }
 
   std::vector<double> scale(P->C);
   for (int c = 0; c < P->C; ++c) scale[c] = freq_hz[c] / (kCLight * params->cell_lambda);
@@ -274,12 +348,12 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
                          hipMemcpyHostToDevice, s));
   RTS_HIP(hipMemcpyAsync(P->d_scale, scale.data(), scale.size() * sizeof(double),
                          hipMemcpyHostToDevice, s));
-  RTS_HIP(hipMemsetAsync(P->d_cursor, 0, (size_t)P->nkeys * sizeof(uint32_t), s));
-  RTS_HIP(hipMemsetAsync(P->d_stats, 0, 8 * sizeof(unsigned long long), s));
+  RTS_HIP(launch_fill_u32(P->d_cursor, P->nkeys, 0u, s));
+  RTS_HIP(launch_fill_u32((uint32_t *)P->d_stats, 16, 0u, s));
 
   PlanArgs pa = plan_args(*P, uvw_m, weights);
   RTS_HIP(launch_plan_count(pa, s));
-  RTS_HIP(launch_scan(P->d_cursor, P->d_tile_off, P->d_cursor, P->d_scan_tmp, P->nkeys, s));
+  RTS_HIP(scan_counts(*P, s));
   unsigned long long stats[8] = {0};
   uint32_t total = 0;
   RTS_HIP(hipMemcpyAsync(stats, P->d_stats, sizeof stats, hipMemcpyDeviceToHost, s));
@@ -289,9 +363,12 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
     set_error("work-list count mismatch (%llu listed, %u scanned)", stats[4], total);
     return RTS_E_HIP;
   }
-  P->list_cap = std::max<int64_t>(total, 1);
+  // headroom for later rts_plan_update calls whose flags or uv coverage differ
+  P->list_cap = std::max<int64_t>((int64_t)total + (int64_t)total / 8 + 1024, 1);
+  P->list_cap = std::min<int64_t>(P->list_cap, (int64_t)UINT32_MAX);
   RTS_HIP(dalloc(&P->d_list, (size_t)P->list_cap));
   pa.list = P->d_list;
+  pa.list_cap = P->list_cap;
   RTS_HIP(launch_plan_scatter(pa, s));
 
   rts_plan_info &I = P->info;
@@ -301,12 +378,28 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   I.n_offgrid = (int64_t)stats[2];
   I.n_segments = (int64_t)stats[3];
   I.n_listings = (int64_t)total;
+  I.n_dropped = 0;
   I.tile = P->tile;
   I.seg_max = P->seg_max;
   I.workspace_bytes = (int64_t)(P->tabE.size() * 4 + P->C * 8 + nsamp * P->ncopy * 2 +
                                 (P->nkeys + 1) * 4 + P->nkeys * 4 + (P->scan_blocks + 1) * 4 + 64 +
                                 P->nkeys * 8 + P->list_cap * 8);
   *out = P.release();
+  return RTS_OK;
+}
+
+rts_status rts_plan_update(rts_plan_t plan, const double *uvw_m, const float *weights, void *stream) {
+  if (rts_status st = check_plan(plan)) return st;
+  RTS_REQUIRE(uvw_m && weights, "uvw_m and weights must be non-NULL");
+  RTS_REQUIRE(aligned(uvw_m, 8) && aligned(weights, 4), "uvw_m / weights are misaligned");
+  hipStream_t s = (hipStream_t)stream;
+  PlanArgs pa = plan_args(*plan, uvw_m, weights);
+  RTS_HIP(launch_fill_u32(plan->d_cursor, plan->nkeys, 0u, s));
+  RTS_HIP(launch_fill_u32((uint32_t *)plan->d_stats, 16, 0u, s));
+  RTS_HIP(launch_plan_count(pa, s));
+  RTS_HIP(scan_counts(*plan, s));
+  RTS_HIP(launch_plan_scatter(pa, s));
+  plan->stats_pending = true;
   return RTS_OK;
 }
 
@@ -395,6 +488,18 @@ rts_status rts_plan_get_table(rts_plan_t plan, float *tab, int64_t capacity) {
 rts_status rts_plan_get_info(rts_plan_t plan, rts_plan_info *info) {
   if (rts_status st = check_plan(plan)) return st;
   RTS_REQUIRE(info != nullptr, "info is NULL");
+  if (plan->stats_pending) {
+    unsigned long long st[8] = {0};
+    RTS_HIP(hipDeviceSynchronize());
+    RTS_HIP(hipMemcpy(st, plan->d_stats, sizeof st, hipMemcpyDeviceToHost));
+    plan->info.n_valid = (int64_t)st[0];
+    plan->info.n_flagged = (int64_t)st[1];
+    plan->info.n_offgrid = (int64_t)st[2];
+    plan->info.n_segments = (int64_t)st[3];
+    plan->info.n_listings = (int64_t)st[4];
+    plan->info.n_dropped = (int64_t)st[5];
+    plan->stats_pending = false;
+  }
   *info = plan->info;
   return RTS_OK;
 }

@@ -15,7 +15,7 @@ namespace rts {
 constexpr int kMaxW = 16;
 constexpr int kMaxOS = 64;
 constexpr int kMaxN = 8192;
-constexpr int kMaxTile = 128;
+constexpr int kMaxTile = 64;     // FP64 tile accumulator: 16*64*64 B = 64 KiB of LDS
 constexpr double kCLight = 299792458.0;
 constexpr int kBlock = 256;          // threads per workgroup of every kernel here
 
@@ -46,11 +46,17 @@ struct PlanArgs {
   uint16_t *coords;       // [C][ncopy][B][T]
   uint2 *list;            // [capacity]
   uint32_t *counts;       // [nkeys] counts (count pass) / cursors (scatter pass)
-  unsigned long long *stats;  // [5]: valid, flagged, offgrid, segments, listings
+  unsigned long long *stats;  // [6]: valid, flagged, offgrid, segments, listings, dropped
+  int64_t list_cap;       // capacity of list; listings beyond it are dropped and counted
   int N, W, OS, WN, r0, h_lo;
   int tile, nT, nT2;
   int C, B, T, ncopy, seg_max;
   int cg, use_lds;
+  int tgroup;             // lanes per track (power of two >= T) for the lane path, 0 = per-track path
+  int nbx;                // chunked sort: track chunks (0 = not used)
+  int64_t chunk;          // chunked sort: tracks per chunk
+  uint32_t *hist;         // chunked sort: [nkeys][nbx] counts
+  const uint32_t *offs;   // chunked sort: [nkeys][nbx] exclusive offsets (+1 total)
 };
 
 struct TileArgs {
@@ -64,6 +70,7 @@ struct TileArgs {
   float2 *model;
   float2 *gout;
   double *chi2_part;         // [nkeys]
+  int64_t list_cap;          // listings at or beyond this index are ignored
   int N, tile, nT, nT2, nkeys;
   int B, T, ncopy;
   int OS2, WNP;
@@ -89,10 +96,16 @@ struct rts_plan_s {
   uint32_t *d_tile_off = nullptr;
   uint32_t *d_cursor = nullptr;
   uint32_t *d_scan_tmp = nullptr;
+  uint32_t *d_hist = nullptr;     // chunked sort counts [nkeys][nbx]
+  uint32_t *d_offs = nullptr;     // chunked sort offsets [nkeys][nbx] + 1
+  int nbx = 0;
+  int64_t chunk = 0;
+  int cg = 1;                     // chunked sort: channels per workgroup
   unsigned long long *d_stats = nullptr;
   double *d_chi2_part = nullptr;
   int64_t list_cap = 0;
   int64_t scan_blocks = 0;
+  bool stats_pending = false;   // an update ran since the statistics were read back
   rts_plan_info info{};
 };
 
@@ -108,9 +121,12 @@ hipError_t launch_plan_count(const PlanArgs &a, hipStream_t s);
 hipError_t launch_plan_scatter(const PlanArgs &a, hipStream_t s);
 hipError_t launch_scan(const uint32_t *counts, uint32_t *tile_off, uint32_t *cursor,
                        uint32_t *tmp, int64_t n, hipStream_t s);
+hipError_t launch_tile_offsets(const uint32_t *offs, int64_t nbx, int64_t nkeys, uint32_t *tile_off,
+                               hipStream_t s);
 hipError_t launch_coords(const double *uvw, const double *scale, const float *w, int32_t *out,
                          int N, int W, int OS, int C, int B, int T, hipStream_t s);
 hipError_t launch_chi2_reduce(const double *part, int64_t n, double *out, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
 // tile kernels (tile_*.hip)
 template <int MODE>

@@ -147,6 +147,16 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
   return t;
 }
 
+__device__ __forceinline__ uint2 make_rec(const PlanArgs &a, int c, int b, int copy,
+                                          const Seg &sg, bool home) {
+  uint2 r;
+  r.x = (uint32_t)((((size_t)c * a.B + b) * a.T) + sg.t0);
+  r.y = (uint32_t)sg.X0 | ((uint32_t)sg.Y0 << kRecYShift) | ((uint32_t)(sg.nt - 1) << kRecNtShift) |
+        ((uint32_t)home << kRecHomeBit) | ((uint32_t)copy << kRecCopyBit) |
+        ((uint32_t)sg.any << kRecAnyBit);
+  return r;
+}
+
 // Pass 1: packed per-sample coordinates, sample statistics and listing counts.
 __global__ __launch_bounds__(kBlock) void k_plan_count(PlanArgs a) {
   extern __shared__ uint32_t hist[];
@@ -213,15 +223,6 @@ __global__ __launch_bounds__(kBlock) void k_plan_count(PlanArgs a) {
   }
 }
 
-__device__ __forceinline__ uint2 make_rec(const PlanArgs &a, int c, int b, int copy,
-                                          const Seg &sg, bool home) {
-  uint2 r;
-  r.x = (uint32_t)((((size_t)c * a.B + b) * a.T) + sg.t0);
-  r.y = (uint32_t)sg.X0 | ((uint32_t)sg.Y0 << kRecYShift) | ((uint32_t)(sg.nt - 1) << kRecNtShift) |
-        ((uint32_t)home << kRecHomeBit) | ((uint32_t)copy << kRecCopyBit) |
-        ((uint32_t)sg.any << kRecAnyBit);
-  return r;
-}
 
 // Pass 2: every listing claims its slot.  With the LDS histogram, a workgroup
 // reserves one contiguous range per key with a single global atomic and hands
@@ -255,9 +256,308 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter(PlanArgs a) {
       for_listings(a, c, copy, sgm, [&](int64_t key, int, int, bool home) {
         const uint32_t pos = a.use_lds ? atomicAdd(&base[key - (int64_t)c0 * a.nT2], 1u)
                                        : atomicAdd(&a.counts[key], 1u);
-        a.list[pos] = make_rec(a, c, b, copy, sgm, home);
+        if ((int64_t)pos < a.list_cap)
+          a.list[pos] = make_rec(a, c, b, copy, sgm, home);
+        else
+          atomicAdd(&a.stats[5], 1ull);
       });
     });
+}
+
+// ------------------------------------------------- lane-per-sample plan (T <= 64)
+// The samples of one track sit in adjacent lanes (a group of `tgroup` lanes, the
+// power of two >= T), so uvw and weight loads are coalesced and every sample's
+// FP64 coordinates are computed once per pass.  Every lane of a group then runs
+// the same greedy segmentation over the group's samples (read with lane
+// shuffles), so each lane learns the segment it belongs to without a leader; the
+// first lane of each segment emits its listings with global atomics.
+struct LaneSeg {
+  int t0, nt, X0, Y0;
+  bool any;
+};
+
+__device__ __forceinline__ LaneSeg lane_segment(const PlanArgs &a, const Sample &sm, int t, int G) {
+  LaneSeg mine{0, 0, 0, 0, false};
+  int t0 = 0;
+  bool any = false;
+  int mnx = 0, mxx = 0, mny = 0, mxy = 0;
+  auto close = [&](int t1) {
+    if (t >= t0 && t < t1) {
+      mine.t0 = t0;
+      mine.nt = t1 - t0;
+      mine.any = any;
+      mine.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
+      mine.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+    }
+  };
+  for (int tt = 0; tt < a.T; ++tt) {
+    const int vv = __shfl((int)sm.valid, tt, G);
+    const int cx = __shfl(sm.cx, tt, G);
+    const int cy = __shfl(sm.cy, tt, G);
+    if (vv) {
+      if (any) {
+        const int nx0 = min(mnx, cx), nx1 = max(mxx, cx);
+        const int ny0 = min(mny, cy), ny1 = max(mxy, cy);
+        if (nx1 - nx0 > 1 || ny1 - ny0 > 1 || tt - t0 >= a.seg_max) {
+          close(tt);
+          t0 = tt;
+          mnx = mxx = cx;
+          mny = mxy = cy;
+        } else {
+          mnx = nx0; mxx = nx1; mny = ny0; mxy = ny1;
+        }
+      } else {
+        if (tt - t0 >= a.seg_max) {
+          close(tt);
+          t0 = tt;
+        }
+        any = true;
+        mnx = mxx = cx;
+        mny = mxy = cy;
+      }
+    } else if (tt - t0 >= a.seg_max) {
+      close(tt);
+      t0 = tt;
+      any = false;
+    }
+  }
+  close(a.T);
+  return mine;
+}
+
+// Min / max over an aligned group of G lanes (G a power of two <= 64), result in
+// every lane of the group.  DPP quad permutations and row mirrors for G <= 16.
+__device__ __forceinline__ int dpp_ctrl_xor(int v, int level) {
+  switch (level) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);   // quad [1,0,3,2]
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);   // quad [2,3,0,1]
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // row_half_mirror
+    default: return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true); // row_mirror
+  }
+}
+
+template <bool MAX>
+__device__ __forceinline__ int group_reduce(int v, int G) {
+  int lvl = 0;
+  for (int w = 2; w <= G && w <= 16; w <<= 1, ++lvl) {
+    const int o = dpp_ctrl_xor(v, lvl);
+    v = MAX ? max(v, o) : min(v, o);
+  }
+  for (int w = 32; w <= G; w <<= 1) {
+    const int o = __shfl_xor(v, w >> 1, 64);
+    v = MAX ? max(v, o) : min(v, o);
+  }
+  return v;
+}
+
+// Segment of lane t: when the whole track fits one segment (at most seg_max
+// samples and its valid samples span at most 2x2 cells), which the greedy walk
+// would also produce, it is found with four group reductions; otherwise the walk
+// runs.  All lanes of the wave must call this (it uses cross-lane operations).
+__device__ __forceinline__ LaneSeg track_segment(const PlanArgs &a, const Sample &sm, int t, int G) {
+  const int big = 1 << 30;
+  const int mnx = group_reduce<false>(sm.valid ? sm.cx : big, G);
+  const int mxx = group_reduce<true>(sm.valid ? sm.cx : -big, G);
+  const int mny = group_reduce<false>(sm.valid ? sm.cy : big, G);
+  const int mxy = group_reduce<true>(sm.valid ? sm.cy : -big, G);
+  const bool any = mxx >= mnx;
+  if (a.T <= a.seg_max && (!any || (mxx - mnx <= 1 && mxy - mny <= 1))) {
+    LaneSeg sg;
+    sg.t0 = 0;
+    sg.nt = a.T;
+    sg.any = any;
+    sg.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
+    sg.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+    return sg;
+  }
+  return lane_segment(a, sm, t, G);
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(kBlock) void k_plan_lanes(PlanArgs a) {
+  const int G = a.tgroup;
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int t = (int)(gid & (G - 1));
+  const int64_t tr = gid / G;                         // track over ncopy * B
+  const bool active = tr < (int64_t)a.ncopy * a.B && t < a.T;
+  const int copy = active ? (int)(tr / a.B) : 0;
+  const int b = active ? (int)(tr - (int64_t)copy * a.B) : 0;
+  double u = 0.0, v = 0.0;
+  if (active) {
+    const double sg = copy ? -1.0 : 1.0;
+    const double *p = a.uvw + ((size_t)b * a.T + t) * 3;
+    u = sg * p[0];
+    v = sg * p[1];
+  }
+  unsigned long long nvalid = 0, nflag = 0, noff = 0, nseg = 0, nlist = 0;
+  const int c0 = blockIdx.y * a.cg;
+  const int c1 = min(a.C, c0 + a.cg);
+  for (int c = c0; c < c1; ++c) {
+    const size_t si = ((size_t)c * a.B + b) * a.T + t;
+    Sample sm;
+    if (active) {
+      sm = sample(a, u, v, a.scale[c], a.w[si]);
+    } else {
+      sm.cx = sm.cy = sm.rx = sm.ry = 0;
+      sm.valid = sm.flagged = false;
+    }
+    const LaneSeg sg = track_segment(a, sm, t, G);
+    if (!active) continue;
+    if (!SCATTER) {
+      uint16_t code = 0;
+      if (sm.valid) {
+        const int dx = sm.cx - (sg.X0 + a.h_lo), dy = sm.cy - (sg.Y0 + a.h_lo);
+        const int sx = dx * a.OS + (sm.rx - a.r0), sy = dy * a.OS + (sm.ry - a.r0);
+        code = (uint16_t)(kCoordValid | (sy << 7) | sx);
+      }
+      a.coords[(((size_t)c * a.ncopy + copy) * a.B + b) * a.T + t] = code;
+      if (copy == 0) {
+        nvalid += sm.valid;
+        nflag += sm.flagged;
+        noff += !sm.valid && !sm.flagged;
+      }
+    }
+    if (t != sg.t0) continue;
+    Seg seg;
+    seg.t0 = sg.t0; seg.nt = sg.nt; seg.any = sg.any; seg.X0 = sg.X0; seg.Y0 = sg.Y0;
+    if (!SCATTER) ++nseg;
+    for_listings(a, c, copy, seg, [&](int64_t key, int, int, bool home) {
+      if (!SCATTER) {
+        ++nlist;
+        atomicAdd(&a.counts[key], 1u);
+      } else {
+        const uint32_t pos = atomicAdd(&a.counts[key], 1u);
+        if ((int64_t)pos < a.list_cap)
+          a.list[pos] = make_rec(a, c, b, copy, seg, home);
+        else
+          atomicAdd(&a.stats[5], 1ull);
+      }
+    });
+  }
+  if (!SCATTER) {
+    const unsigned long long v0 = block_sum_u64(nvalid);
+    const unsigned long long v1 = block_sum_u64(nflag);
+    const unsigned long long v2 = block_sum_u64(noff);
+    const unsigned long long v3 = block_sum_u64(nseg);
+    const unsigned long long v4 = block_sum_u64(nlist);
+    if (threadIdx.x == 0) {
+      if (v0) atomicAdd(&a.stats[0], v0);
+      if (v1) atomicAdd(&a.stats[1], v1);
+      if (v2) atomicAdd(&a.stats[2], v2);
+      if (v3) atomicAdd(&a.stats[3], v3);
+      if (v4) atomicAdd(&a.stats[4], v4);
+    }
+  }
+}
+
+// ------------------------------------------- chunked counting sort (T <= 64)
+// Workgroup (bx, by) owns a contiguous chunk of tracks and a group of cg
+// channels.  Pass 1 counts its listings per (channel, tile) key in an LDS
+// histogram and writes the whole histogram to hist[key][bx] (key-major, no
+// atomics).  One exclusive scan over hist in (key, bx) order gives every
+// workgroup the first slot of each key in the sorted list; pass 2 recomputes the
+// same listings and claims slots from LDS copies of those offsets.
+template <bool SCATTER>
+__global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
+  extern __shared__ uint32_t bins[];                 // [cg][nT2]
+  const int G = a.tgroup;
+  const int c0 = blockIdx.y * a.cg;
+  const int c1 = min(a.C, c0 + a.cg);
+  const int nloc = (c1 - c0) * a.nT2;
+  const int bx = blockIdx.x;
+  if (!SCATTER) {
+    for (int i = threadIdx.x; i < nloc; i += kBlock) bins[i] = 0u;
+  } else {
+    for (int i = threadIdx.x; i < nloc; i += kBlock)
+      bins[i] = a.offs[((size_t)c0 * a.nT2 + i) * a.nbx + bx];
+  }
+  __syncthreads();
+  const int64_t ntr = (int64_t)a.ncopy * a.B;
+  const int64_t tr_beg = (int64_t)bx * a.chunk;
+  const int64_t tr_end = min(ntr, tr_beg + a.chunk);
+  const int per_iter = kBlock / G;
+  const int t = threadIdx.x & (G - 1);
+  unsigned long long nvalid = 0, nflag = 0, noff = 0, nseg = 0, nlist = 0;
+  for (int64_t base = tr_beg; base < tr_end; base += per_iter) {
+    const int64_t tr = base + threadIdx.x / G;
+    const bool active = tr < tr_end && t < a.T;
+    const int copy = active ? (int)(tr / a.B) : 0;
+    const int b = active ? (int)(tr - (int64_t)copy * a.B) : 0;
+    double u = 0.0, v = 0.0;
+    if (active) {
+      const double sg = copy ? -1.0 : 1.0;
+      const double *p = a.uvw + ((size_t)b * a.T + t) * 3;
+      u = sg * p[0];
+      v = sg * p[1];
+    }
+    for (int c = c0; c < c1; ++c) {
+      const size_t si = ((size_t)c * a.B + b) * a.T + t;
+      Sample sm;
+      if (active) {
+        sm = sample(a, u, v, a.scale[c], a.w[si]);
+      } else {
+        sm.cx = sm.cy = sm.rx = sm.ry = 0;
+        sm.valid = sm.flagged = false;
+      }
+      const LaneSeg sg = track_segment(a, sm, t, G);
+      if (!active) continue;
+      if (!SCATTER) {
+        uint16_t code = 0;
+        if (sm.valid) {
+          const int dx = sm.cx - (sg.X0 + a.h_lo), dy = sm.cy - (sg.Y0 + a.h_lo);
+          const int sx = dx * a.OS + (sm.rx - a.r0), sy = dy * a.OS + (sm.ry - a.r0);
+          code = (uint16_t)(kCoordValid | (sy << 7) | sx);
+        }
+        a.coords[(((size_t)c * a.ncopy + copy) * a.B + b) * a.T + t] = code;
+        if (copy == 0) {
+          nvalid += sm.valid;
+          nflag += sm.flagged;
+          noff += !sm.valid && !sm.flagged;
+        }
+      }
+      if (t != sg.t0) continue;
+      Seg seg;
+      seg.t0 = sg.t0; seg.nt = sg.nt; seg.any = sg.any; seg.X0 = sg.X0; seg.Y0 = sg.Y0;
+      if (!SCATTER) ++nseg;
+      for_listings(a, c, copy, seg, [&](int64_t key, int, int, bool home) {
+        const int bin = (int)(key - (int64_t)c0 * a.nT2);
+        if (!SCATTER) {
+          ++nlist;
+          atomicAdd(&bins[bin], 1u);
+        } else {
+          const uint32_t pos = atomicAdd(&bins[bin], 1u);
+          if ((int64_t)pos < a.list_cap)
+            a.list[pos] = make_rec(a, c, b, copy, seg, home);
+          else
+            atomicAdd(&a.stats[5], 1ull);
+        }
+      });
+    }
+  }
+  if (!SCATTER) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nloc; i += kBlock)
+      a.hist[((size_t)c0 * a.nT2 + i) * a.nbx + bx] = bins[i];
+    const unsigned long long v0 = block_sum_u64(nvalid);
+    const unsigned long long v1 = block_sum_u64(nflag);
+    const unsigned long long v2 = block_sum_u64(noff);
+    const unsigned long long v3 = block_sum_u64(nseg);
+    const unsigned long long v4 = block_sum_u64(nlist);
+    if (threadIdx.x == 0) {
+      if (v0) atomicAdd(&a.stats[0], v0);
+      if (v1) atomicAdd(&a.stats[1], v1);
+      if (v2) atomicAdd(&a.stats[2], v2);
+      if (v3) atomicAdd(&a.stats[3], v3);
+      if (v4) atomicAdd(&a.stats[4], v4);
+    }
+  }
+}
+
+// tile_off[key] = offs[key * nbx] (the first slot of the key), tile_off[nkeys] = total.
+__global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t *offs, int64_t nbx, int64_t nkeys,
+                                                         uint32_t *tile_off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= nkeys) tile_off[i] = offs[i * nbx];
 }
 
 // ---------------------------------------------------------------- exclusive scan
@@ -325,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *tile_off, uint32_
   if (i < n) {
     const uint32_t v = tile_off[i] + bsum[i / kScanPerBlock];
     tile_off[i] = v;
-    cursor[i] = v;
+    if (cursor) cursor[i] = v;
   }
   if (i == 0) tile_off[n] = bsum[nb];
 }
@@ -365,9 +665,30 @@ __global__ __launch_bounds__(1024) void k_chi2_reduce(const double *part, int64_
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 }  // namespace
 
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_plan_count(const PlanArgs &a, hipStream_t s) {
+  if (a.nbx > 0) {
+    dim3 g3((unsigned)a.nbx, (a.C + a.cg - 1) / a.cg);
+    hipLaunchKernelGGL(k_plan_chunk<false>, g3, dim3(kBlock), (size_t)a.cg * a.nT2 * sizeof(uint32_t), s, a);
+    return hipGetLastError();
+  }
+  if (a.tgroup > 0) {
+    const int64_t lanes = (int64_t)a.ncopy * a.B * a.tgroup;
+    dim3 g2((unsigned)((lanes + kBlock - 1) / kBlock), (a.C + a.cg - 1) / a.cg);
+    hipLaunchKernelGGL(k_plan_lanes<false>, g2, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
   dim3 grid((a.B * a.ncopy + kBlock - 1) / kBlock, (a.C + a.cg - 1) / a.cg);
   const size_t lds = a.use_lds ? (size_t)a.cg * a.nT2 * sizeof(uint32_t) : 0;
   hipLaunchKernelGGL(k_plan_count, grid, dim3(kBlock), lds, s, a);
@@ -375,6 +696,17 @@ hipError_t launch_plan_count(const PlanArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_plan_scatter(const PlanArgs &a, hipStream_t s) {
+  if (a.nbx > 0) {
+    dim3 g3((unsigned)a.nbx, (a.C + a.cg - 1) / a.cg);
+    hipLaunchKernelGGL(k_plan_chunk<true>, g3, dim3(kBlock), (size_t)a.cg * a.nT2 * sizeof(uint32_t), s, a);
+    return hipGetLastError();
+  }
+  if (a.tgroup > 0) {
+    const int64_t lanes = (int64_t)a.ncopy * a.B * a.tgroup;
+    dim3 g2((unsigned)((lanes + kBlock - 1) / kBlock), (a.C + a.cg - 1) / a.cg);
+    hipLaunchKernelGGL(k_plan_lanes<true>, g2, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  }
   dim3 grid((a.B * a.ncopy + kBlock - 1) / kBlock, (a.C + a.cg - 1) / a.cg);
   const size_t lds = a.use_lds ? (size_t)a.cg * a.nT2 * sizeof(uint32_t) : 0;
   hipLaunchKernelGGL(k_plan_scatter, grid, dim3(kBlock), lds, s, a);
@@ -388,6 +720,13 @@ hipError_t launch_scan(const uint32_t *counts, uint32_t *tile_off, uint32_t *cur
   hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kBlock), 0, s, tmp, nb);
   hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                      tile_off, cursor, (const uint32_t *)tmp, n, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_offsets(const uint32_t *offs, int64_t nbx, int64_t nkeys, uint32_t *tile_off,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((nkeys + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     offs, nbx, nkeys, tile_off);
   return hipGetLastError();
 }
 

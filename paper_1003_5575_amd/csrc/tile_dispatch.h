@@ -6,22 +6,26 @@
 
 namespace rts {
 
-#define RTS_TILE_CASE(WNV, SM)                                                               \
-  case (WNV)*16 + (SM): {                                                                    \
-    if (lds > 65536) {                                                                       \
-      hipError_t e = hipFuncSetAttribute((const void *)k_tile<WNV, SM, MODE>,                \
+#define RTS_TILE_LAUNCH(WNV, SM, BLK)                                                          \
+  {                                                                                            \
+    if (lds > 65536) {                                                                         \
+      hipError_t e = hipFuncSetAttribute((const void *)k_tile<WNV, SM, MODE, BLK>,             \
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-      if (e != hipSuccess) return e;                                                         \
-    }                                                                                        \
-    hipLaunchKernelGGL((k_tile<WNV, SM, MODE>), dim3(nblk), dim3(kBlock), lds, s, a);       \
-    break;                                                                                   \
+      if (e != hipSuccess) return e;                                                           \
+    }                                                                                          \
+    hipLaunchKernelGGL((k_tile<WNV, SM, MODE, BLK>), dim3(nblk), dim3(BLK), lds, s, a);       \
   }
+#define RTS_TILE_CASE(WNV, SM)                                   \
+  case (WNV)*16 + (SM):                                          \
+    if (P.tile <= 32) RTS_TILE_LAUNCH(WNV, SM, 128)              \
+    else RTS_TILE_LAUNCH(WNV, SM, 256)                           \
+    break;
 
 template <int MODE>
 hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s) {
   const unsigned nblk = (unsigned)P.nkeys;
   size_t lds = (size_t)a.OS2 * a.WNP * sizeof(float);
-  if (MODE != kDegrid) lds += (size_t)2 * P.tile * P.tile * sizeof(float);
+  if (MODE != kDegrid) lds += (size_t)2 * P.tile * P.tile * sizeof(double);
   switch (P.WN * 16 + P.seg_max) {
     RTS_TILE_CASE(3, 4) RTS_TILE_CASE(3, 8)
     RTS_TILE_CASE(4, 4) RTS_TILE_CASE(4, 8)
@@ -39,5 +43,6 @@ hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s) {
 }
 
 #undef RTS_TILE_CASE
+#undef RTS_TILE_LAUNCH
 
 }  // namespace rts

@@ -4,10 +4,10 @@
 // it read only the visibilities binned near it, staging them in shared memory.
 // Here a workgroup owns a tile x tile square of one channel's grid in LDS
 // (complex FP32 accumulator, no global atomics on grid data) and walks the work
-// list of segments whose (W+1)x(W+1) window touches the tile.  One lane handles
-// one segment: up to SMAX consecutive samples of one baseline that share the
-// window, so the kernel rows, the G_in window rows and the accumulated window
-// rows are reused across the samples in registers.  A segment whose window
+// list of segments whose (W+1)x(W+1) window touches the tile.  A quad of lanes
+// handles one segment: up to SMAX consecutive samples of one baseline that share
+// the window, so the G_in window and the accumulated update stay in registers
+// across the samples and reach LDS once per segment.  A segment whose window
 // crosses a tile edge is listed in every tile it touches; each copy adds only the
 // cells of its own tile, so every output cell has exactly one writer.
 //
@@ -29,11 +29,43 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-template <int WN, int SMAX, int MODE>
-__global__ __launch_bounds__(kBlock) void k_tile(TileArgs a) {
-  extern __shared__ float smem[];
-  float *tabE = smem;                        // [2*OS][WNP]
-  float *acc = smem + a.OS2 * a.WNP;         // [tile*tile][2]  (kGrid, kFused)
+// Lanes per segment and window columns per lane.  A group of kGroup adjacent
+// lanes shares one segment; lane q of the group owns window columns q*CPL ..
+// q*CPL+CPL-1, holds those columns of the G_in window and of the accumulated
+// update in registers, and the degridded value of each sample is the sum of the
+// group's partial sums (two butterfly steps inside a quad of lanes).
+constexpr int kGroup = 4;
+
+// Minimum waves per SIMD the register allocation of the tile kernel targets.
+#ifndef RTS_TILE_WAVES
+#define RTS_TILE_WAVES 4
+#endif
+
+// Butterfly partners inside a quad of lanes through DPP quad permutations (no LDS
+// traffic, unlike a generic lane shuffle).
+__device__ __forceinline__ float quad_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float quad_xor2(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+}
+
+template <int WN>
+struct Cols {
+  static constexpr int CPL = (WN + kGroup - 1) / kGroup;
+};
+
+template <int WN, int SMAX, int MODE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RTS_TILE_WAVES))) void k_tile(TileArgs a) {
+  constexpr int CPL = Cols<WN>::CPL;
+  constexpr bool kFullCols = (WN % kGroup) == 0;   // every lane's columns lie in the window
+  extern __shared__ float4 smem4[];
+  float *smem = reinterpret_cast<float *>(smem4);
+  float *tabE = smem;                        // [2*OS][WNP], rows 16-byte aligned
+  // FP64 accumulator [tile][tile][2] (kGrid, kFused).  LDS float atomics are an
+  // order of magnitude slower than FP64 ones on this GPU; FP64 also keeps the
+  // tile sums nearly independent of the order the work list is visited in.
+  double *acc = reinterpret_cast<double *>(smem + a.OS2 * a.WNP);
   const int key = xcd_remap(blockIdx.x, gridDim.x);
   const int c = key / a.nT2;
   const int rem = key - c * a.nT2;
@@ -42,17 +74,25 @@ __global__ __launch_bounds__(kBlock) void k_tile(TileArgs a) {
   const int x0 = tx * T, y0 = ty * T;
   const int TT = T * T;
 
-  for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += kBlock) tabE[i] = a.tabE[i];
+  for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += BLOCK) tabE[i] = a.tabE[i];
   if (MODE != kDegrid)
-    for (int i = threadIdx.x; i < 2 * TT; i += kBlock) acc[i] = 0.0f;
+    for (int i = threadIdx.x; i < 2 * TT; i += BLOCK) acc[i] = 0.0;
   __syncthreads();
 
-  const uint32_t beg = a.tile_off[key], end = a.tile_off[key + 1];
+  const uint32_t cap = (uint32_t)a.list_cap;
+  const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
   const size_t copy_stride = (size_t)a.B * a.T;
+  const int q = threadIdx.x & (kGroup - 1);       // lane within the group
+  const int col0 = q * CPL;                       // first window column of this lane
   double chi2 = 0.0;
 
-  for (uint32_t k = beg + threadIdx.x; k < end; k += kBlock) {
-    const uint2 rec = a.list[k];
+  constexpr uint32_t kStride = BLOCK / kGroup;
+  uint32_t k = beg + threadIdx.x / kGroup;
+  uint2 rec_next = make_uint2(0u, 0u);
+  if (k < end) rec_next = a.list[k];
+  for (; k < end; k += kStride) {
+    const uint2 rec = rec_next;
+    if (k + kStride < end) rec_next = a.list[k + kStride];   // prefetch the next record
     const bool home = (rec.y >> kRecHomeBit) & 1u;
     if (MODE == kDegrid && !home) continue;
     const int X0 = (int)(rec.y & kRecXMask);
@@ -64,109 +104,135 @@ __global__ __launch_bounds__(kBlock) void k_tile(TileArgs a) {
     const bool put_model = home && copy == 0 && (MODE == kDegrid || (MODE == kFused && a.write_model));
     if (!any) {
       if (put_model)
-        for (int s = 0; s < nt; ++s) a.model[vi + s] = make_float2(0.0f, 0.0f);
+        for (int s = q; s < nt; s += kGroup) a.model[vi + s] = make_float2(0.0f, 0.0f);
       continue;
     }
     const size_t ci = vi + (size_t)(c * (a.ncopy - 1) + copy) * copy_stride;
 
-    float kx[SMAX][WN], ky[SMAX][WN];
-    float2 val[SMAX];
-    float wt[SMAX];
-    bool ok[SMAX];
+    // Issue every global load of the segment before any arithmetic: the packed
+    // coordinates, visibilities and weights of all its samples and this lane's
+    // columns of the G_in window.
+    uint32_t cws[SMAX];
+    float2 vs[SMAX];
+    float ws[SMAX];
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
-      ok[s] = false;
-      val[s] = make_float2(0.0f, 0.0f);
-      wt[s] = 0.0f;
-      int sx = 0, sy = 0;
+      cws[s] = 0u;
+      vs[s] = make_float2(0.0f, 0.0f);
+      ws[s] = 0.0f;
       if (s < nt) {
-        const uint16_t cw = a.coords[ci + s];
-        ok[s] = (cw & kCoordValid) != 0;
-        sx = cw & 0x7F;
-        sy = (cw >> 7) & 0x7F;
-        if (MODE != kDegrid && ok[s]) {
-          val[s] = a.vis[vi + s];
-          wt[s] = a.w[vi + s];
-          if (copy) val[s].y = -val[s].y;
+        cws[s] = a.coords[ci + s];
+        if (MODE != kDegrid) {
+          vs[s] = a.vis[vi + s];
+          ws[s] = a.w[vi + s];
         }
       }
-      const float *rx = tabE + sx * a.WNP;
-      const float *ry = tabE + sy * a.WNP;
-#pragma unroll
-      for (int i = 0; i < WN; ++i) {
-        kx[s][i] = rx[i];
-        ky[s][i] = ok[s] ? ry[i] : 0.0f;
-      }
     }
-
-    float2 M[SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) M[s] = make_float2(0.0f, 0.0f);
+    float2 gw[WN][CPL];
     if (MODE != kGrid) {
-      const float2 *g = a.gin + ((size_t)c * a.N + Y0) * a.N + X0;
+      const float2 *g = a.gin + ((size_t)c * a.N + Y0) * a.N + X0 + col0;
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
-        float2 row[WN];
 #pragma unroll
-        for (int i = 0; i < WN; ++i) row[i] = g[(size_t)j * a.N + i];
+        for (int i = 0; i < CPL; ++i)
+          gw[j][i] = (kFullCols || col0 + i < WN) ? g[i] : make_float2(0.0f, 0.0f);
+        g += a.N;
+      }
+    }
+    float2 up[WN][CPL];
+    if (MODE != kDegrid) {
 #pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-          if (s < nt) {
-            float rr = 0.0f, ri = 0.0f;
+      for (int j = 0; j < WN; ++j)
 #pragma unroll
-            for (int i = 0; i < WN; ++i) {
-              rr = fmaf(kx[s][i], row[i].x, rr);
-              ri = fmaf(kx[s][i], row[i].y, ri);
+        for (int i = 0; i < CPL; ++i) up[j][i] = make_float2(0.0f, 0.0f);
+    }
+
+    float chi2_seg = 0.0f;   // this segment's sum of w |r|^2 (SMAX terms, FP32)
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      if (s < nt) {
+        const uint32_t cw = cws[s];
+        const bool ok = (cw & kCoordValid) != 0;
+        const int sx = cw & 0x7F, sy = (cw >> 7) & 0x7F;
+        float ky[(WN + 3) & ~3], kx[CPL];
+        const float4 *ry = reinterpret_cast<const float4 *>(tabE + sy * a.WNP);
+#pragma unroll
+        for (int j4 = 0; j4 < (WN + 3) / 4; ++j4) {
+          const float4 t4 = ry[j4];
+          ky[4 * j4] = t4.x;
+          ky[4 * j4 + 1] = t4.y;
+          ky[4 * j4 + 2] = t4.z;
+          ky[4 * j4 + 3] = t4.w;
+        }
+        const float *rx = tabE + sx * a.WNP + col0;
+        if (CPL == 2 && kFullCols) {
+          const float2 t2 = *reinterpret_cast<const float2 *>(rx);
+          kx[0] = t2.x;
+          kx[CPL - 1] = t2.y;
+        } else {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) kx[i] = (kFullCols || col0 + i < WN) ? rx[i] : 0.0f;
+        }
+
+        float2 m = make_float2(0.0f, 0.0f);
+        if (MODE != kGrid) {
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) {
+            float hr = 0.0f, hi = 0.0f;
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+              hr = fmaf(ky[j], gw[j][i].x, hr);
+              hi = fmaf(ky[j], gw[j][i].y, hi);
             }
-            M[s].x = fmaf(ky[s][j], rr, M[s].x);
-            M[s].y = fmaf(ky[s][j], ri, M[s].y);
+            m.x = fmaf(kx[i], hr, m.x);
+            m.y = fmaf(kx[i], hi, m.y);
+          }
+          m.x += quad_xor1(m.x);
+          m.y += quad_xor1(m.y);
+          m.x += quad_xor2(m.x);
+          m.y += quad_xor2(m.y);
+          if (put_model && q == 0) a.model[vi + s] = ok ? m : make_float2(0.0f, 0.0f);
+        }
+        if (MODE != kDegrid && ok) {
+          float2 v = vs[s];
+          const float wt = ws[s];
+          if (copy) v.y = -v.y;
+          float ar, ai;
+          if (MODE == kGrid) {
+            ar = wt * v.x;
+            ai = wt * v.y;
+          } else {
+            const float rr = v.x - m.x, ri = v.y - m.y;
+            ar = wt * rr;
+            ai = wt * ri;
+            chi2_seg = fmaf(wt, fmaf(rr, rr, ri * ri), chi2_seg);
+          }
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) {
+            const float br = ar * kx[i], bi = ai * kx[i];
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+              up[j][i].x = fmaf(br, ky[j], up[j][i].x);
+              up[j][i].y = fmaf(bi, ky[j], up[j][i].y);
+            }
           }
         }
       }
     }
 
-    float2 A[SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      A[s] = make_float2(0.0f, 0.0f);
-      if (ok[s]) {
-        if (MODE == kGrid) {
-          A[s] = make_float2(wt[s] * val[s].x, wt[s] * val[s].y);
-        } else if (MODE == kFused) {
-          const float rr = val[s].x - M[s].x, ri = val[s].y - M[s].y;
-          A[s] = make_float2(wt[s] * rr, wt[s] * ri);
-          if (home && copy == 0) chi2 += (double)wt[s] * ((double)rr * rr + (double)ri * ri);
-        }
-      }
-      if (put_model && s < nt) a.model[vi + s] = ok[s] ? M[s] : make_float2(0.0f, 0.0f);
-    }
-
+    if (MODE == kFused && home && q == 0) chi2 += (double)chi2_seg;
     if (MODE != kDegrid) {
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         const int yy = Y0 + j - y0;
         if ((unsigned)yy < (unsigned)T) {
-          float2 arow[WN];
 #pragma unroll
-          for (int i = 0; i < WN; ++i) arow[i] = make_float2(0.0f, 0.0f);
-#pragma unroll
-          for (int s = 0; s < SMAX; ++s) {
-            if (s < nt) {
-              const float br = A[s].x * ky[s][j], bi = A[s].y * ky[s][j];
-#pragma unroll
-              for (int i = 0; i < WN; ++i) {
-                arow[i].x = fmaf(br, kx[s][i], arow[i].x);
-                arow[i].y = fmaf(bi, kx[s][i], arow[i].y);
-              }
-            }
-          }
-          float *dst = acc + 2 * (yy * T + (X0 - x0));
-#pragma unroll
-          for (int i = 0; i < WN; ++i) {
-            const int xx = X0 + i - x0;
-            if ((unsigned)xx < (unsigned)T) {
-              atomicAdd(dst + 2 * i, arow[i].x);
-              atomicAdd(dst + 2 * i + 1, arow[i].y);
+          for (int i = 0; i < CPL; ++i) {
+            const int xx = X0 + col0 + i - x0;
+            if ((kFullCols || col0 + i < WN) && (unsigned)xx < (unsigned)T) {
+              double *dst = acc + 2 * (yy * T + xx);
+              atomicAdd(dst, (double)up[j][i].x);
+              atomicAdd(dst + 1, (double)up[j][i].y);
             }
           }
         }
@@ -175,24 +241,26 @@ __global__ __launch_bounds__(kBlock) void k_tile(TileArgs a) {
   }
 
   if (MODE == kFused) {
-    __shared__ double red[kBlock / 64];
+    __shared__ double red[BLOCK / 64];
     for (int o = 32; o > 0; o >>= 1) chi2 += __shfl_down(chi2, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = chi2;
     __syncthreads();
     if (threadIdx.x == 0) {
       double t = 0.0;
-      for (int i = 0; i < kBlock / 64; ++i) t += red[i];
+      for (int i = 0; i < BLOCK / 64; ++i) t += red[i];
       a.chi2_part[key] = t;
     }
   }
   if (MODE != kDegrid) {
     __syncthreads();
     float4 *out = reinterpret_cast<float4 *>(a.gout);
-    const float4 *src = reinterpret_cast<const float4 *>(acc);
+    const double4 *src = reinterpret_cast<const double4 *>(acc);
     const int half = T / 2;
-    for (int i = threadIdx.x; i < TT / 2; i += kBlock) {
+    for (int i = threadIdx.x; i < TT / 2; i += BLOCK) {
       const int yy = i / half, xx = i - yy * half;
-      out[(((size_t)c * a.N + y0 + yy) * a.N + x0) / 2 + xx] = src[i];
+      const double4 d = src[i];
+      out[(((size_t)c * a.N + y0 + yy) * a.N + x0) / 2 + xx] =
+          make_float4((float)d.x, (float)d.y, (float)d.z, (float)d.w);
     }
   }
 }

@@ -168,3 +168,39 @@ def test_repeat_calls_are_stable(rts):
     a = plan.grid(vis, w).cpu().numpy()
     b = plan.grid(vis, w).cpu().numpy()
     assert rel_l2(a, b) <= 1e-6
+
+
+def test_plan_update_matches_fresh_plan(rts):
+    """Re-planning in place for a new cadence gives the fresh plan's results."""
+    wl, freq, du = small_case(n_ant=40, channels=(0, 13, 31), N=256, weights="uniform", flag_frac=0.1)
+    wl2, _, _ = small_case(seed=5, n_ant=40, channels=(0, 13, 31), N=256, weights="uniform", flag_frac=0.1)
+    uvw, vis, w = to_dev(torch, wl)
+    uvw2, vis2, w2 = to_dev(torch, wl2)
+    plan = rts.GridPlan(uvw, freq, w, 256, du)
+    plan.update(uvw2, w2)
+    G = plan.grid(vis2, w2).cpu().numpy()
+    info = plan.info
+    assert info["n_dropped"] == 0
+    geom = O.Geometry(wl2.uvw_m, freq, wl2.weights, 256, du)
+    Gref = O.grid(geom, wl2.vis, wl2.weights)
+    for c in range(3):
+        assert rel_l2(G[c], Gref[c]) <= RTOL_L2
+    assert info["n_valid"] == int(geom.valid.sum())
+
+
+def test_plan_update_overflow_is_reported_not_fatal(rts):
+    """A cadence that needs more work-list entries than the plan holds drops the
+    excess, reports it, and stays in bounds."""
+    wl, freq, du = small_case(n_ant=60, channels=(0, 31), N=256)
+    uvw, vis, w = to_dev(torch, wl)
+    w0 = torch.zeros_like(w)
+    # every sample flagged: one listing per track; 16-cell tiles later double that
+    plan = rts.GridPlan(uvw, freq, w0, 256, du, tile=16)
+    cap_listings = plan.info["n_listings"]
+    plan.update(uvw, w)
+    G = plan.grid(vis, w)
+    torch.cuda.synchronize()
+    info = plan.info
+    assert info["n_listings"] > cap_listings
+    assert info["n_dropped"] > 0
+    assert torch.isfinite(torch.view_as_real(G)).all()
