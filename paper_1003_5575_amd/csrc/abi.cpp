@@ -138,6 +138,7 @@ void free_plan(Plan *P) {
   hipFree(P->d_scan_tmp);
   hipFree(P->d_hist);
   hipFree(P->d_offs);
+  hipFree(P->d_desc);
   hipFree(P->d_stats);
   hipFree(P->d_chi2_part);
   delete P;
@@ -188,6 +189,9 @@ PlanArgs plan_args(const Plan &P, const double *uvw, const float *w) {
   a.stats = P.d_stats;
   a.list_cap = P.list_cap;
   a.N = P.N; a.W = P.W; a.OS = P.OS; a.WN = P.WN; a.r0 = P.r0; a.h_lo = P.h_lo;
+  a.log2os = -1;
+  for (int l = 0; l <= 6; ++l)
+    if ((1 << l) == P.OS) a.log2os = l;
   a.tile = P.tile; a.nT = P.nT; a.nT2 = P.nT2;
   a.C = P.C; a.B = P.B; a.T = P.T; a.ncopy = P.ncopy; a.seg_max = P.seg_max;
   // Tracks of up to 64 samples: one lane per sample, channels in groups of 8 so
@@ -203,6 +207,7 @@ PlanArgs plan_args(const Plan &P, const double *uvw, const float *w) {
   a.chunk = P.chunk;
   a.hist = P.d_hist;
   a.offs = P.d_offs;
+  a.desc = P.d_desc;
   if (P.nbx > 0) {
     a.use_lds = 0;
     a.cg = P.cg;
@@ -340,6 +345,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   if (P->nbx > 0) {
     RTS_HIP(dalloc(&P->d_hist, (size_t)nscan));
     RTS_HIP(dalloc(&P->d_offs, (size_t)nscan + 1));
+    RTS_HIP(dalloc(&P->d_desc, (size_t)P->C * P->ncopy * P->B));
   }
 
   std::vector<double> scale(P->C);
@@ -383,6 +389,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   I.seg_max = P->seg_max;
   I.workspace_bytes = (int64_t)(P->tabE.size() * 4 + P->C * 8 + nsamp * P->ncopy * 2 +
                                 (P->nkeys + 1) * 4 + P->nkeys * 4 + (P->scan_blocks + 1) * 4 + 64 +
+                                (P->nbx > 0 ? (2 * nscan + 1) * 4 + (int64_t)P->C * P->ncopy * P->B * 4 : 0) +
                                 P->nkeys * 8 + P->list_cap * 8);
   *out = P.release();
   return RTS_OK;

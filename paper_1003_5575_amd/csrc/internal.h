@@ -39,6 +39,11 @@ constexpr int kRecAnyBit = 31;
 //   the sample's cell offset from the window origin + h_lo, r its kernel phase.
 constexpr uint16_t kCoordValid = 0x8000u;
 
+// Per-track segment descriptor written by the first plan pass (chunked sort):
+// X0 | Y0 << 13 | any << 30 for a track that is one segment, kDescMulti otherwise.
+constexpr int kDescAnyBit = 30;
+constexpr uint32_t kDescMulti = 0x80000000u;
+
 struct PlanArgs {
   const double *uvw;      // [B][T][3]
   const double *scale;    // [C]  f_c / (c du)
@@ -49,6 +54,7 @@ struct PlanArgs {
   unsigned long long *stats;  // [6]: valid, flagged, offgrid, segments, listings, dropped
   int64_t list_cap;       // capacity of list; listings beyond it are dropped and counted
   int N, W, OS, WN, r0, h_lo;
+  int log2os;             // log2(OS) when OS is a power of two, else -1
   int tile, nT, nT2;
   int C, B, T, ncopy, seg_max;
   int cg, use_lds;
@@ -57,6 +63,7 @@ struct PlanArgs {
   int64_t chunk;          // chunked sort: tracks per chunk
   uint32_t *hist;         // chunked sort: [nkeys][nbx] counts
   const uint32_t *offs;   // chunked sort: [nkeys][nbx] exclusive offsets (+1 total)
+  uint32_t *desc;         // chunked sort: per-track segment descriptors [C][ncopy][B]
 };
 
 struct TileArgs {
@@ -98,6 +105,7 @@ struct rts_plan_s {
   uint32_t *d_scan_tmp = nullptr;
   uint32_t *d_hist = nullptr;     // chunked sort counts [nkeys][nbx]
   uint32_t *d_offs = nullptr;     // chunked sort offsets [nkeys][nbx] + 1
+  uint32_t *d_desc = nullptr;     // chunked sort per-track descriptors [C][ncopy][B]
   int nbx = 0;
   int64_t chunk = 0;
   int cg = 1;                     // chunked sort: channels per workgroup

@@ -29,10 +29,14 @@ __device__ __forceinline__ bool snap(double u, double v, double s, int N, int OS
   return true;
 }
 
-// Split an oversampled coordinate into cell and phase r in [r0, r0 + OS).
-__device__ __forceinline__ void split(int xs, int r0, int OS, int &cell, int &r) {
+// Split an oversampled coordinate into cell and phase r in [r0, r0 + OS)
+// (floor division; an arithmetic shift when OS is a power of two).
+__device__ __forceinline__ void split(int xs, int r0, int OS, int log2os, int &cell, int &r) {
   const int q = xs - r0;
-  cell = (q >= 0) ? q / OS : -((-q + OS - 1) / OS);
+  if (log2os >= 0)
+    cell = q >> log2os;
+  else
+    cell = (q >= 0) ? q / OS : -((-q + OS - 1) / OS);
   r = xs - cell * OS;
 }
 
@@ -47,8 +51,8 @@ __device__ __forceinline__ Sample sample(const PlanArgs &a, double u, double v, 
   Sample o;
   int xs, ys;
   const bool fin = snap(u, v, s, a.N, a.OS, xs, ys);
-  split(xs, a.r0, a.OS, o.cx, o.rx);
-  split(ys, a.r0, a.OS, o.cy, o.ry);
+  split(xs, a.r0, a.OS, a.log2os, o.cx, o.rx);
+  split(ys, a.r0, a.OS, a.log2os, o.cy, o.ry);
   const bool on = fin && o.cx - a.h_lo >= 0 && o.cx - a.h_lo + a.W - 1 <= a.N - 1 &&
                   o.cy - a.h_lo >= 0 && o.cy - a.h_lo + a.W - 1 <= a.N - 1;
   o.flagged = (w == 0.0f);
@@ -274,10 +278,11 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter(PlanArgs a) {
 struct LaneSeg {
   int t0, nt, X0, Y0;
   bool any;
+  bool single;   // the whole track is this one segment
 };
 
 __device__ __forceinline__ LaneSeg lane_segment(const PlanArgs &a, const Sample &sm, int t, int G) {
-  LaneSeg mine{0, 0, 0, 0, false};
+  LaneSeg mine{0, 0, 0, 0, false, false};
   int t0 = 0;
   bool any = false;
   int mnx = 0, mxx = 0, mny = 0, mxy = 0;
@@ -368,6 +373,7 @@ __device__ __forceinline__ LaneSeg track_segment(const PlanArgs &a, const Sample
     sg.any = any;
     sg.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
     sg.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+    sg.single = true;
     return sg;
   }
   return lane_segment(a, sm, t, G);
@@ -515,6 +521,10 @@ __global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
           noff += !sm.valid && !sm.flagged;
         }
       }
+      if (!SCATTER && t == 0)
+        a.desc[((size_t)c * a.ncopy + copy) * a.B + b] =
+            sg.single ? ((uint32_t)sg.any << kDescAnyBit) | ((uint32_t)sg.Y0 << kRecYShift) | (uint32_t)sg.X0
+                      : kDescMulti;
       if (t != sg.t0) continue;
       Seg seg;
       seg.t0 = sg.t0; seg.nt = sg.nt; seg.any = sg.any; seg.X0 = sg.X0; seg.Y0 = sg.Y0;
@@ -549,6 +559,49 @@ __global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
       if (v2) atomicAdd(&a.stats[2], v2);
       if (v3) atomicAdd(&a.stats[3], v3);
       if (v4) atomicAdd(&a.stats[4], v4);
+    }
+  }
+}
+
+// Pass 2 of the chunked sort, one thread per track: a single-segment track is
+// emitted from the descriptor written by pass 1; a track that pass 1 split into
+// several segments is walked again from uvw and the weights (same greedy rule).
+__global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
+  extern __shared__ uint32_t bins[];
+  const int c0 = blockIdx.y * a.cg;
+  const int c1 = min(a.C, c0 + a.cg);
+  const int nloc = (c1 - c0) * a.nT2;
+  const int bx = blockIdx.x;
+  for (int i = threadIdx.x; i < nloc; i += kBlock)
+    bins[i] = a.offs[((size_t)c0 * a.nT2 + i) * a.nbx + bx];
+  __syncthreads();
+  const int64_t ntr = (int64_t)a.ncopy * a.B;
+  const int64_t tr_end = min(ntr, (int64_t)bx * a.chunk + a.chunk);
+  for (int64_t tr = (int64_t)bx * a.chunk + threadIdx.x; tr < tr_end; tr += kBlock) {
+    const int copy = (int)(tr / a.B);
+    const int b = (int)(tr - (int64_t)copy * a.B);
+    for (int c = c0; c < c1; ++c) {
+      auto emit = [&](const Seg &seg) {
+        for_listings(a, c, copy, seg, [&](int64_t key, int, int, bool home) {
+          const uint32_t pos = atomicAdd(&bins[(int)(key - (int64_t)c0 * a.nT2)], 1u);
+          if ((int64_t)pos < a.list_cap)
+            a.list[pos] = make_rec(a, c, b, copy, seg, home);
+          else
+            atomicAdd(&a.stats[5], 1ull);
+        });
+      };
+      const uint32_t d = a.desc[((size_t)c * a.ncopy + copy) * a.B + b];
+      if (d != kDescMulti) {
+        Seg seg;
+        seg.t0 = 0;
+        seg.nt = a.T;
+        seg.any = (d >> kDescAnyBit) & 1u;
+        seg.X0 = (int)(d & kRecXMask);
+        seg.Y0 = (int)((d >> kRecYShift) & kRecXMask);
+        emit(seg);
+      } else {
+        walk_track(a, c, b, copy, emit);
+      }
     }
   }
 }
@@ -643,6 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_coords(const double *uvw, const doub
   a.N = N; a.W = W; a.OS = OS;
   a.r0 = (W & 1) ? -(OS / 2) : 0;
   a.h_lo = (W & 1) ? (W - 1) / 2 : W / 2 - 1;
+  a.log2os = -1;
   int xs, ys;
   const bool fin = snap(uvw[bt * 3], uvw[bt * 3 + 1], scale[c], N, OS, xs, ys);
   const Sample sm = sample(a, uvw[bt * 3], uvw[bt * 3 + 1], scale[c], w[i]);
@@ -698,7 +752,7 @@ hipError_t launch_plan_count(const PlanArgs &a, hipStream_t s) {
 hipError_t launch_plan_scatter(const PlanArgs &a, hipStream_t s) {
   if (a.nbx > 0) {
     dim3 g3((unsigned)a.nbx, (a.C + a.cg - 1) / a.cg);
-    hipLaunchKernelGGL(k_plan_chunk<true>, g3, dim3(kBlock), (size_t)a.cg * a.nT2 * sizeof(uint32_t), s, a);
+    hipLaunchKernelGGL(k_plan_scatter_tracks, g3, dim3(kBlock), (size_t)a.cg * a.nT2 * sizeof(uint32_t), s, a);
     return hipGetLastError();
   }
   if (a.tgroup > 0) {

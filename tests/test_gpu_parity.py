@@ -204,3 +204,21 @@ def test_plan_update_overflow_is_reported_not_fatal(rts):
     assert info["n_listings"] > cap_listings
     assert info["n_dropped"] > 0
     assert torch.isfinite(torch.view_as_real(G)).all()
+
+
+@pytest.mark.parametrize("cadence_s,T", [(4000.0, 8), (20000.0, 16)])
+def test_fast_moving_tracks_split_into_segments(rts, cadence_s, T):
+    """Tracks that cross several cells per step are cut into many segments (the
+    plan's multi-segment path); results still match the oracle."""
+    from synth import mwa
+    cfg = mwa.Config("fast", 36, T, 2, 140e6, 15e6, 256, 7, 8, n_sources=1, cadence_s=cadence_s)
+    wl = mwa.make_workload(cfg, seed=3)
+    freq = wl.freq_hz
+    du = fit_cell(wl.uvw_m, freq, 256, 7)
+    rng = np.random.default_rng(1)
+    wl.weights = rng.uniform(0.5, 1.5, wl.weights.shape).astype(np.float32)
+    wl.weights[rng.random(wl.weights.shape) < 0.1] = 0
+    plan, G, Gin, M, fused = run_all(rts, wl, freq, du, 256, 7, 8, tile=32)
+    info = plan.info
+    assert info["n_segments"] > 2 * wl.vis.shape[0] * wl.vis.shape[1]   # most tracks split
+    check_against_oracle(wl, freq, du, 256, 7, 8, G, Gin, M, fused)
