@@ -146,7 +146,7 @@ void free_plan(Plan *P) {
 
 // Channels per workgroup of the chunked sort: its LDS histogram holds cg * nT2
 // counters (at most 8192, 32 KiB).
-int chunk_channels(int nT2) { return std::max(1, std::min(8, 8192 / nT2)); }
+int chunk_channels(int nT2) { return std::max(1, std::min(kMaxCg, 8192 / nT2)); }
 
 // Choose the chunked counting sort when the tracks are short enough for the lane
 // path and one channel's tiles fit the LDS histogram; the (key, chunk) count
@@ -192,6 +192,9 @@ PlanArgs plan_args(const Plan &P, const double *uvw, const float *w) {
   a.log2os = -1;
   for (int l = 0; l <= 6; ++l)
     if ((1 << l) == P.OS) a.log2os = l;
+  a.log2tile = -1;
+  for (int l = 1; l <= 13; ++l)
+    if ((1 << l) == P.tile) a.log2tile = l;
   a.tile = P.tile; a.nT = P.nT; a.nT2 = P.nT2;
   a.C = P.C; a.B = P.B; a.T = P.T; a.ncopy = P.ncopy; a.seg_max = P.seg_max;
   // Tracks of up to 64 samples: one lane per sample, channels in groups of 8 so

@@ -18,6 +18,7 @@ constexpr int kMaxN = 8192;
 constexpr int kMaxTile = 64;     // FP64 tile accumulator: 16*64*64 B = 64 KiB of LDS
 constexpr double kCLight = 299792458.0;
 constexpr int kBlock = 256;          // threads per workgroup of every kernel here
+constexpr int kMaxCg = 8;            // most channels one plan workgroup handles
 
 enum Mode { kGrid = 0, kDegrid = 1, kFused = 2 };
 
@@ -56,6 +57,7 @@ struct PlanArgs {
   int N, W, OS, WN, r0, h_lo;
   int log2os;             // log2(OS) when OS is a power of two, else -1
   int tile, nT, nT2;
+  int log2tile;           // log2(tile) when tile is a power of two, else -1
   int C, B, T, ncopy, seg_max;
   int cg, use_lds;
   int tgroup;             // lanes per track (power of two >= T) for the lane path, 0 = per-track path

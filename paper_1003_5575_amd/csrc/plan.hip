@@ -131,8 +131,14 @@ __device__ __forceinline__ void for_listings(const PlanArgs &a, int c, int copy,
     if (copy == 0) fn((int64_t)c * a.nT2, 0, 0, true);
     return;
   }
-  const int tx0 = sg.X0 / a.tile, tx1 = (sg.X0 + a.WN - 1) / a.tile;
-  const int ty0 = sg.Y0 / a.tile, ty1 = (sg.Y0 + a.WN - 1) / a.tile;
+  int tx0, tx1, ty0, ty1;
+  if (a.log2tile >= 0) {
+    tx0 = sg.X0 >> a.log2tile; tx1 = (sg.X0 + a.WN - 1) >> a.log2tile;
+    ty0 = sg.Y0 >> a.log2tile; ty1 = (sg.Y0 + a.WN - 1) >> a.log2tile;
+  } else {
+    tx0 = sg.X0 / a.tile; tx1 = (sg.X0 + a.WN - 1) / a.tile;
+    ty0 = sg.Y0 / a.tile; ty1 = (sg.Y0 + a.WN - 1) / a.tile;
+  }
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx)
       fn((int64_t)c * a.nT2 + ty * a.nT + tx, tx, ty, tx == tx0 && ty == ty0);
@@ -496,11 +502,12 @@ __global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
       u = sg * p[0];
       v = sg * p[1];
     }
+#pragma unroll 1
     for (int c = c0; c < c1; ++c) {
-      const size_t si = ((size_t)c * a.B + b) * a.T + t;
+      const float wt = active ? a.w[((size_t)c * a.B + b) * a.T + t] : 0.0f;
       Sample sm;
       if (active) {
-        sm = sample(a, u, v, a.scale[c], a.w[si]);
+        sm = sample(a, u, v, a.scale[c], wt);
       } else {
         sm.cx = sm.cy = sm.rx = sm.ry = 0;
         sm.valid = sm.flagged = false;

@@ -222,19 +222,36 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RTS_TILE_
 
     if (MODE == kFused && home && q == 0) chi2 += (double)chi2_seg;
     if (MODE != kDegrid) {
+      // Add this lane's window columns to the tile accumulator.  Windows entirely
+      // inside the tile (most of them) skip the per-cell bounds checks.
+      const int lx = X0 + col0 - x0, ly = Y0 - y0;
+      const bool inside = (unsigned)(X0 - x0) <= (unsigned)(T - WN) && (unsigned)ly <= (unsigned)(T - WN);
+      double *row = acc + 2 * (ly * T + lx);      // dereferenced only inside the tile
+      if (inside) {
 #pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        const int yy = Y0 + j - y0;
-        if ((unsigned)yy < (unsigned)T) {
+        for (int j = 0; j < WN; ++j) {
 #pragma unroll
           for (int i = 0; i < CPL; ++i) {
-            const int xx = X0 + col0 + i - x0;
-            if ((kFullCols || col0 + i < WN) && (unsigned)xx < (unsigned)T) {
-              double *dst = acc + 2 * (yy * T + xx);
-              atomicAdd(dst, (double)up[j][i].x);
-              atomicAdd(dst + 1, (double)up[j][i].y);
+            if (kFullCols || col0 + i < WN) {
+              atomicAdd(row + 2 * i, (double)up[j][i].x);
+              atomicAdd(row + 2 * i + 1, (double)up[j][i].y);
             }
           }
+          row += 2 * T;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          if ((unsigned)(ly + j) < (unsigned)T) {
+#pragma unroll
+            for (int i = 0; i < CPL; ++i) {
+              if ((kFullCols || col0 + i < WN) && (unsigned)(lx + i) < (unsigned)T) {
+                atomicAdd(row + 2 * i, (double)up[j][i].x);
+                atomicAdd(row + 2 * i + 1, (double)up[j][i].y);
+              }
+            }
+          }
+          row += 2 * T;
         }
       }
     }
