@@ -68,6 +68,22 @@ def touched_cells(uvw_m, freq_hz, N, du, W, OS):
     return total
 
 
+def measured_traffic():
+    """HBM bytes per launch of the fused kernel from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_tile_fused_single_cadence_traffic.json")
+    src = os.path.join(ROOT, "paper_1003_5575_amd", "csrc", "tile_kernel.h")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("tile_kernel_h_sha256") != sha:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +95,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-channels", type=int, default=16)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB buffer 5 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; the channel-sharded multi-GPU "
@@ -89,6 +107,14 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 1 << 30, "copies": 5}))
+        return
     import paper_1003_5575_amd as rts
     from synth import make_workload
 
@@ -178,7 +204,7 @@ def main():
     alg_bytes = n_valid * (8 + 4 + 8) + grid_cells * 8 + touched * 8
     achieved = alg_bytes / (fused_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": "k_tile<8,8,kFused>", "kernel_ms": round(fused_ms, 4),
                 "alg_bytes_per_launch": int(alg_bytes), "touched_cells": int(touched),
                 "full_grid_read_frac": round((n_valid * 20 + 2 * grid_cells * 8) / (fused_ms * 1e-3) / 1e9

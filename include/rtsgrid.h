@@ -135,6 +135,11 @@ rts_status rts_compute_coords(const rts_params *params, const double *uvw_m,
                               const double *freq_hz, const float *weights, int32_t *out,
                               void *stream);
 
+/* mask[c][b][t] (device, C*B*T bytes) = 1 where the sample is valid for this plan
+ * (w != 0 at plan time and every tap on the grid), else 0.  Used for the
+ * gradients of the chi-squared step, whose residual is zero at invalid samples. */
+rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream);
+
 /* Copy the FP32 kernel table tab[p][j] = k(t_j - r_p/OS) (OS rows, W columns; rows
  * are phases r0..r0+OS-1, columns taps t0..t0+W-1 with r0 = -(OS/2), t0 = -(W-1)/2
  * for odd W and r0 = 0, t0 = -W/2+1 for even W) into host memory `tab`

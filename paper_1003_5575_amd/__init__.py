@@ -16,7 +16,8 @@ import ctypes
 from . import _lib
 from ._lib import RtsError, RtsParams, RtsPlanInfo  # noqa: F401
 
-__all__ = ["GridPlan", "compute_coords", "RtsError", "library_path", "version"]
+__all__ = ["GridPlan", "compute_coords", "RtsError", "library_path", "version", "GridFn", "DegridFn",
+           "Chi2Fn", "grid", "degrid", "chi2"]
 
 
 def _torch():
@@ -107,6 +108,13 @@ class GridPlan:
         inf = RtsPlanInfo()
         _lib.check(_lib.load().rts_plan_get_info(self.handle, ctypes.byref(inf)), "rts_plan_get_info")
         return {k: getattr(inf, k) for k, _ in RtsPlanInfo._fields_}
+
+    def valid_mask(self, stream=None):
+        """bool [C][B][T]: samples this plan grids (w != 0 at plan time, all taps on the grid)."""
+        torch = _torch()
+        out = torch.empty((self.C, self.B, self.T), dtype=torch.uint8, device=self.device)
+        _lib.check(_lib.load().rts_plan_valid_mask(self.handle, _ptr(out), _stream(stream)), "rts_plan_valid_mask")
+        return out.bool()
 
     def table(self):
         import numpy as np
@@ -213,3 +221,6 @@ def compute_coords(uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversa
     _lib.check(_lib.load().rts_compute_coords(ctypes.byref(p), _ptr(uvw), ctypes.cast(fr, ctypes.c_void_p),
                                               _ptr(weights), _ptr(out), _stream(stream)), "rts_compute_coords")
     return out
+
+
+from .autograd import Chi2Fn, DegridFn, GridFn, chi2, degrid, grid  # noqa: E402,F401

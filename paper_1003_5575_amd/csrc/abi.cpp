@@ -486,6 +486,14 @@ rts_status rts_compute_coords(const rts_params *params, const double *uvw_m, con
   return RTS_OK;
 }
 
+rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream) {
+  if (rts_status st = check_plan(plan)) return st;
+  RTS_REQUIRE(mask != nullptr, "mask is NULL");
+  const int64_t n = (int64_t)plan->C * plan->B * plan->T;
+  RTS_HIP(launch_valid_mask(plan->d_coords, mask, plan->B, plan->T, plan->ncopy, n, (hipStream_t)stream));
+  return RTS_OK;
+}
+
 rts_status rts_plan_get_table(rts_plan_t plan, float *tab, int64_t capacity) {
   if (rts_status st = check_plan(plan)) return st;
   RTS_REQUIRE(tab != nullptr, "tab is NULL");

@@ -136,6 +136,8 @@ hipError_t launch_tile_offsets(const uint32_t *offs, int64_t nbx, int64_t nkeys,
 hipError_t launch_coords(const double *uvw, const double *scale, const float *w, int32_t *out,
                          int N, int W, int OS, int C, int B, int T, hipStream_t s);
 hipError_t launch_chi2_reduce(const double *part, int64_t n, double *out, hipStream_t s);
+hipError_t launch_valid_mask(const uint16_t *coords, uint8_t *mask, int B, int T, int ncopy, int64_t n,
+                             hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
 // tile kernels (tile_*.hip)

@@ -712,6 +712,16 @@ __global__ __launch_bounds__(kBlock) void k_coords(const double *uvw, const doub
   out[i * 3 + 2] = sm.valid ? 1 : 0;
 }
 
+// mask[c][b][t] = 1 for valid samples of the +uv copy (from the packed coordinates).
+__global__ __launch_bounds__(kBlock) void k_valid_mask(const uint16_t *coords, uint8_t *mask, int B, int T,
+                                                       int ncopy, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t bt = (int64_t)B * T;
+  const int64_t c = i / bt;
+  mask[i] = (coords[i + c * (ncopy - 1) * bt] & kCoordValid) ? 1 : 0;
+}
+
 __global__ __launch_bounds__(1024) void k_chi2_reduce(const double *part, int64_t n, double *out) {
   __shared__ double red[16];
   double s = 0.0;
@@ -796,6 +806,13 @@ hipError_t launch_coords(const double *uvw, const double *scale, const float *w,
   const int64_t n = (int64_t)C * B * T;
   hipLaunchKernelGGL(k_coords, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, uvw,
                      scale, w, out, N, W, OS, C, B, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_valid_mask(const uint16_t *coords, uint8_t *mask, int B, int T, int ncopy, int64_t n,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_valid_mask, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, coords, mask,
+                     B, T, ncopy, n);
   return hipGetLastError();
 }
 

@@ -1,0 +1,118 @@
+"""Autograd through the HIP kernels: gradients against the FP64 oracle's
+analytic gradients and against central finite differences of the oracle's
+chi-squared on random grid cells."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_helpers import RTOL_L2, rel_l2, small_case, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rts():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1003_5575_amd as rts
+    rts._lib.load()
+    return rts
+
+
+def setup(rts, seed=0, N=256, n_ant=40, channels=(0, 17, 31)):
+    wl, freq, du = small_case(seed=seed, n_ant=n_ant, channels=channels, N=N, weights="uniform", flag_frac=0.1,
+                              offgrid_frac=0.02)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, N, du)
+    geom = O.Geometry(wl.uvw_m, freq, wl.weights, N, du)
+    return wl, freq, du, uvw, vis, w, plan, geom
+
+
+def test_valid_mask_matches_oracle(rts):
+    wl, freq, du, uvw, vis, w, plan, geom = setup(rts)
+    assert np.array_equal(plan.valid_mask().cpu().numpy(), geom.valid)
+
+
+def test_degrid_backward_is_grid(rts):
+    wl, freq, du, uvw, vis, w, plan, geom = setup(rts, seed=1)
+    rng = np.random.default_rng(1)
+    G0 = (rng.standard_normal((3, 256, 256)) + 1j * rng.standard_normal((3, 256, 256))).astype(np.complex64)
+    y = (rng.standard_normal(wl.vis.shape) + 1j * rng.standard_normal(wl.vis.shape)).astype(np.complex64)
+    G = torch.from_numpy(G0).cuda().requires_grad_(True)
+    yt = torch.from_numpy(y).cuda()
+    M = rts.degrid(G, plan)
+    loss = (torch.conj(yt) * M).real.sum()
+    loss.backward()
+    ref = O.grid(geom, np.where(geom.valid, y, 0), np.ones_like(wl.weights))
+    for c in range(3):
+        assert rel_l2(G.grad[c].cpu().numpy(), ref[c]) <= RTOL_L2
+
+
+def test_grid_backward_matches_oracle_vjp(rts):
+    wl, freq, du, uvw, vis, w, plan, geom = setup(rts, seed=2)
+    rng = np.random.default_rng(2)
+    Gt = (rng.standard_normal((3, 256, 256)) + 1j * rng.standard_normal((3, 256, 256))).astype(np.complex64)
+    V = vis.clone().requires_grad_(True)
+    wt = w.clone().requires_grad_(True)
+    G = rts.grid(V, wt, plan)
+    loss = (G - torch.from_numpy(Gt).cuda()).abs().pow(2).sum()
+    loss.backward()
+    Gref = O.grid(geom, wl.vis, wl.weights)
+    gV, gw = O.grid_vjp(geom, wl.vis, wl.weights, 2.0 * (Gref - Gt))
+    for c in range(3):
+        assert rel_l2(V.grad[c].cpu().numpy(), gV[c]) <= RTOL_L2
+        assert rel_l2(wt.grad[c].cpu().numpy(), gw[c]) <= RTOL_L2
+
+
+def test_chi2_gradients_match_oracle(rts):
+    wl, freq, du, uvw, vis, w, plan, geom = setup(rts, seed=3)
+    rng = np.random.default_rng(3)
+    G0 = (0.1 * (rng.standard_normal((3, 256, 256)) + 1j * rng.standard_normal((3, 256, 256)))).astype(np.complex64)
+    G = torch.from_numpy(G0).cuda().requires_grad_(True)
+    V = vis.clone().requires_grad_(True)
+    wt = w.clone().requires_grad_(True)
+    loss = rts.chi2(V, wt, G, plan)
+    loss.backward()
+    chi2, gG, gw, gV = O.chi2_gradients(geom, wl.vis, wl.weights, G0.astype(np.complex128))
+    assert abs(loss.item() - chi2) <= RTOL_L2 * chi2
+    for c in range(3):
+        assert rel_l2(G.grad[c].cpu().numpy(), gG[c]) <= RTOL_L2
+        assert rel_l2(wt.grad[c].cpu().numpy(), gw[c]) <= RTOL_L2
+        assert rel_l2(V.grad[c].cpu().numpy(), gV[c]) <= RTOL_L2
+
+
+def test_chi2_grad_against_oracle_finite_differences_on_64_cells(rts):
+    """Central differences of the FP64 oracle's chi-squared (exact for a quadratic)
+    at 64 random grid cells under the footprint, Re and Im separately."""
+    wl, freq, du, uvw, vis, w, plan, geom = setup(rts, seed=4, N=128, n_ant=20, channels=(9,))
+    rng = np.random.default_rng(4)
+    G0 = (0.1 * (rng.standard_normal((1, 128, 128)) + 1j * rng.standard_normal((1, 128, 128)))).astype(np.complex64)
+    G = torch.from_numpy(G0).cuda().requires_grad_(True)
+    loss = rts.chi2(vis, w, G, plan)
+    loss.backward()
+    grad = G.grad.cpu().numpy()
+    cover = np.argwhere(np.abs(O.grid(geom, np.ones_like(wl.vis), np.ones_like(wl.weights))) > 0)
+    cells = cover[rng.choice(len(cover), 64, replace=False)]
+    G64 = G0.astype(np.complex128)
+    h = 1e-3 * np.sqrt(np.mean(np.abs(G64) ** 2))
+    scale = np.max(np.abs(grad))
+    for (c, yy, xx) in cells:
+        for unit in (1.0, 1j):
+            Gp = G64.copy(); Gp[c, yy, xx] += h * unit
+            Gm = G64.copy(); Gm[c, yy, xx] -= h * unit
+            fd = (O.grid_degrid(geom, wl.vis, wl.weights, Gp)[2] - O.grid_degrid(geom, wl.vis, wl.weights, Gm)[2]) / (2 * h)
+            got = grad[c, yy, xx].real if unit == 1.0 else grad[c, yy, xx].imag
+            assert abs(got - fd) <= 1e-5 * scale + 1e-5 * abs(fd)
+
+
+def test_adjoint_identity_on_gpu(rts):
+    """<grid_w(x), y> = <x, w * degrid(y)> with both sides from the HIP kernels."""
+    wl, freq, du, uvw, vis, w, plan, geom = setup(rts, seed=5)
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy((rng.standard_normal(wl.vis.shape) + 1j * rng.standard_normal(wl.vis.shape)).astype(np.complex64)).cuda()
+    y = torch.from_numpy((rng.standard_normal((3, 256, 256)) + 1j * rng.standard_normal((3, 256, 256))).astype(np.complex64)).cuda()
+    lhs = torch.vdot(plan.grid(x, w).flatten().to(torch.complex128), y.flatten().to(torch.complex128))
+    rhs = torch.vdot(x.flatten().to(torch.complex128), (w * plan.degrid(y)).flatten().to(torch.complex128))
+    scale = plan.grid(x, w).abs().pow(2).sum().sqrt().item() * y.abs().pow(2).sum().sqrt().item()
+    assert abs((lhs - rhs).item()) <= 1e-6 * scale
