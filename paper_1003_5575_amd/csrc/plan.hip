@@ -570,6 +570,130 @@ __global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
   }
 }
 
+// Pass 1 of the chunked sort for tracks of at most kTrackRegs samples: one thread
+// per track keeps the track's coordinates in registers (no cross-lane work), so
+// each sample's FP64 coordinates are computed once and the listing bookkeeping
+// is done once per track.  Tracks that split into several segments (rare) are
+// walked again from memory with the same greedy rule.
+constexpr int kTrackRegs = 8;
+
+__global__ __launch_bounds__(kBlock) void k_plan_track_count(PlanArgs a) {
+  extern __shared__ uint32_t bins[];                 // [cg][nT2]
+  const int c0 = blockIdx.y * a.cg;
+  const int c1 = min(a.C, c0 + a.cg);
+  const int nloc = (c1 - c0) * a.nT2;
+  const int bx = blockIdx.x;
+  for (int i = threadIdx.x; i < nloc; i += kBlock) bins[i] = 0u;
+  __syncthreads();
+  const int64_t ntr = (int64_t)a.ncopy * a.B;
+  const int64_t tr_end = min(ntr, (int64_t)bx * a.chunk + a.chunk);
+  unsigned long long nvalid = 0, nflag = 0, noff = 0, nseg = 0, nlist = 0;
+  for (int64_t tr = (int64_t)bx * a.chunk + threadIdx.x; tr < tr_end; tr += kBlock) {
+    const int copy = (int)(tr / a.B);
+    const int b = (int)(tr - (int64_t)copy * a.B);
+    const double sgn = copy ? -1.0 : 1.0;
+    double u[kTrackRegs], v[kTrackRegs];
+#pragma unroll
+    for (int t = 0; t < kTrackRegs; ++t) {
+      u[t] = v[t] = 0.0;
+      if (t < a.T) {
+        const double *p = a.uvw + ((size_t)b * a.T + t) * 3;
+        u[t] = sgn * p[0];
+        v[t] = sgn * p[1];
+      }
+    }
+#pragma unroll 1
+    for (int c = c0; c < c1; ++c) {
+      const size_t base = ((size_t)c * a.B + b) * a.T;
+      const double sc = a.scale[c];
+      Sample sm[kTrackRegs];
+      int mnx = 1 << 30, mxx = -(1 << 30), mny = 1 << 30, mxy = -(1 << 30);
+#pragma unroll
+      for (int t = 0; t < kTrackRegs; ++t) {
+        sm[t].valid = sm[t].flagged = false;
+        sm[t].cx = sm[t].cy = sm[t].rx = sm[t].ry = 0;
+        if (t < a.T) {
+          sm[t] = sample(a, u[t], v[t], sc, a.w[base + t]);
+          if (copy == 0) {
+            nvalid += sm[t].valid;
+            nflag += sm[t].flagged;
+            noff += !sm[t].valid && !sm[t].flagged;
+          }
+          if (sm[t].valid) {
+            mnx = min(mnx, sm[t].cx); mxx = max(mxx, sm[t].cx);
+            mny = min(mny, sm[t].cy); mxy = max(mxy, sm[t].cy);
+          }
+        }
+      }
+      const bool any = mxx >= mnx;
+      uint16_t *co = a.coords + (((size_t)c * a.ncopy + copy) * a.B + b) * a.T;
+      const size_t di = ((size_t)c * a.ncopy + copy) * a.B + b;
+      auto count = [&](const Seg &seg) {
+        ++nseg;
+        for_listings(a, c, copy, seg, [&](int64_t key, int, int, bool) {
+          ++nlist;
+          atomicAdd(&bins[(int)(key - (int64_t)c0 * a.nT2)], 1u);
+        });
+      };
+      if (a.T <= a.seg_max && (!any || (mxx - mnx <= 1 && mxy - mny <= 1))) {
+        Seg seg;
+        seg.t0 = 0;
+        seg.nt = a.T;
+        seg.any = any;
+        seg.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
+        seg.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+#pragma unroll
+        for (int t = 0; t < kTrackRegs; ++t) {
+          if (t < a.T) {
+            uint16_t code = 0;
+            if (sm[t].valid) {
+              const int sx = (sm[t].cx - (seg.X0 + a.h_lo)) * a.OS + (sm[t].rx - a.r0);
+              const int sy = (sm[t].cy - (seg.Y0 + a.h_lo)) * a.OS + (sm[t].ry - a.r0);
+              code = (uint16_t)(kCoordValid | (sy << 7) | sx);
+            }
+            co[t] = code;
+          }
+        }
+        a.desc[di] = ((uint32_t)any << kDescAnyBit) | ((uint32_t)seg.Y0 << kRecYShift) | (uint32_t)seg.X0;
+        count(seg);
+      } else {
+        a.desc[di] = kDescMulti;
+        const double sg2 = sgn;
+        const double *uv = a.uvw + (size_t)b * a.T * 3;
+        const float *wrow = a.w + base;
+        walk_track(a, c, b, copy, [&](const Seg &seg) {
+          for (int t = seg.t0; t < seg.t0 + seg.nt; ++t) {
+            const Sample s2 = sample(a, sg2 * uv[t * 3], sg2 * uv[t * 3 + 1], sc, wrow[t]);
+            uint16_t code = 0;
+            if (s2.valid) {
+              const int sx = (s2.cx - (seg.X0 + a.h_lo)) * a.OS + (s2.rx - a.r0);
+              const int sy = (s2.cy - (seg.Y0 + a.h_lo)) * a.OS + (s2.ry - a.r0);
+              code = (uint16_t)(kCoordValid | (sy << 7) | sx);
+            }
+            co[t] = code;
+          }
+          count(seg);
+        });
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nloc; i += kBlock)
+    a.hist[((size_t)c0 * a.nT2 + i) * a.nbx + bx] = bins[i];
+  const unsigned long long v0 = block_sum_u64(nvalid);
+  const unsigned long long v1 = block_sum_u64(nflag);
+  const unsigned long long v2 = block_sum_u64(noff);
+  const unsigned long long v3 = block_sum_u64(nseg);
+  const unsigned long long v4 = block_sum_u64(nlist);
+  if (threadIdx.x == 0) {
+    if (v0) atomicAdd(&a.stats[0], v0);
+    if (v1) atomicAdd(&a.stats[1], v1);
+    if (v2) atomicAdd(&a.stats[2], v2);
+    if (v3) atomicAdd(&a.stats[3], v3);
+    if (v4) atomicAdd(&a.stats[4], v4);
+  }
+}
+
 // Pass 2 of the chunked sort, one thread per track: a single-segment track is
 // emitted from the descriptor written by pass 1; a track that pass 1 split into
 // several segments is walked again from uvw and the weights (same greedy rule).
@@ -751,7 +875,11 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
 hipError_t launch_plan_count(const PlanArgs &a, hipStream_t s) {
   if (a.nbx > 0) {
     dim3 g3((unsigned)a.nbx, (a.C + a.cg - 1) / a.cg);
-    hipLaunchKernelGGL(k_plan_chunk<false>, g3, dim3(kBlock), (size_t)a.cg * a.nT2 * sizeof(uint32_t), s, a);
+    const size_t lds = (size_t)a.cg * a.nT2 * sizeof(uint32_t);
+    if (a.T <= kTrackRegs)
+      hipLaunchKernelGGL(k_plan_track_count, g3, dim3(kBlock), lds, s, a);
+    else
+      hipLaunchKernelGGL(k_plan_chunk<false>, g3, dim3(kBlock), lds, s, a);
     return hipGetLastError();
   }
   if (a.tgroup > 0) {

@@ -6,19 +6,23 @@
 
 namespace rts {
 
-#define RTS_TILE_LAUNCH(WNV, SM, BLK)                                                          \
+#define RTS_TILE_LAUNCH(WNV, SM, BLK, GRP)                                                     \
   {                                                                                            \
     if (lds > 65536) {                                                                         \
-      hipError_t e = hipFuncSetAttribute((const void *)k_tile<WNV, SM, MODE, BLK>,             \
+      hipError_t e = hipFuncSetAttribute((const void *)k_tile<WNV, SM, MODE, BLK, GRP>,        \
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
       if (e != hipSuccess) return e;                                                           \
     }                                                                                          \
-    hipLaunchKernelGGL((k_tile<WNV, SM, MODE, BLK>), dim3(nblk), dim3(BLK), lds, s, a);       \
+    hipLaunchKernelGGL((k_tile<WNV, SM, MODE, BLK, GRP>), dim3(nblk), dim3(BLK), lds, s, a);  \
   }
-#define RTS_TILE_CASE(WNV, SM)                                   \
-  case (WNV)*16 + (SM):                                          \
-    if (P.tile <= 32) RTS_TILE_LAUNCH(WNV, SM, 128)              \
-    else RTS_TILE_LAUNCH(WNV, SM, 256)                           \
+#ifndef RTS_SMALL_W_GROUP
+#define RTS_SMALL_W_GROUP 4
+#endif
+// Windows up to 9 columns: RTS_SMALL_W_GROUP lanes per segment; wider: 4 lanes.
+#define RTS_TILE_CASE(WNV, SM)                                                        \
+  case (WNV)*16 + (SM):                                                               \
+    if (P.tile <= 32) RTS_TILE_LAUNCH(WNV, SM, 128, ((WNV) <= 9 ? RTS_SMALL_W_GROUP : 4)) \
+    else RTS_TILE_LAUNCH(WNV, SM, 256, ((WNV) <= 9 ? RTS_SMALL_W_GROUP : 4))             \
     break;
 
 template <int MODE>

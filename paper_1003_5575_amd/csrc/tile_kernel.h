@@ -29,13 +29,11 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-// Lanes per segment and window columns per lane.  A group of kGroup adjacent
+// Lanes per segment and window columns per lane.  A group of GROUP adjacent
 // lanes shares one segment; lane q of the group owns window columns q*CPL ..
 // q*CPL+CPL-1, holds those columns of the G_in window and of the accumulated
 // update in registers, and the degridded value of each sample is the sum of the
-// group's partial sums (two butterfly steps inside a quad of lanes).
-constexpr int kGroup = 4;
-
+// group's partial sums (butterfly steps inside the group of lanes).
 // Minimum waves per SIMD the register allocation of the tile kernel targets.
 #ifndef RTS_TILE_WAVES
 #define RTS_TILE_WAVES 4
@@ -50,14 +48,12 @@ __device__ __forceinline__ float quad_xor2(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
 }
 
-template <int WN>
-struct Cols {
-  static constexpr int CPL = (WN + kGroup - 1) / kGroup;
-};
-
-template <int WN, int SMAX, int MODE, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RTS_TILE_WAVES))) void k_tile(TileArgs a) {
-  constexpr int CPL = Cols<WN>::CPL;
+template <int WN, int SMAX, int MODE, int BLOCK, int GROUP>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 4 ? RTS_TILE_WAVES : 2))) void k_tile(
+    TileArgs a) {
+  // GROUP lanes (2 or 4) share a segment; each owns CPL window columns.
+  constexpr int kGroup = GROUP;
+  constexpr int CPL = (WN + kGroup - 1) / kGroup;
   constexpr bool kFullCols = (WN % kGroup) == 0;   // every lane's columns lie in the window
   extern __shared__ float4 smem4[];
   float *smem = reinterpret_cast<float *>(smem4);
@@ -169,6 +165,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RTS_TILE_
           const float2 t2 = *reinterpret_cast<const float2 *>(rx);
           kx[0] = t2.x;
           kx[CPL - 1] = t2.y;
+        } else if (CPL == 4 && kFullCols) {
+          const float4 t4 = *reinterpret_cast<const float4 *>(rx);
+          kx[0] = t4.x;
+          kx[1 % CPL] = t4.y;
+          kx[2 % CPL] = t4.z;
+          kx[3 % CPL] = t4.w;
         } else {
 #pragma unroll
           for (int i = 0; i < CPL; ++i) kx[i] = (kFullCols || col0 + i < WN) ? rx[i] : 0.0f;
@@ -189,8 +191,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(RTS_TILE_
           }
           m.x += quad_xor1(m.x);
           m.y += quad_xor1(m.y);
-          m.x += quad_xor2(m.x);
-          m.y += quad_xor2(m.y);
+          if (kGroup == 4) {
+            m.x += quad_xor2(m.x);
+            m.y += quad_xor2(m.y);
+          }
           if (put_model && q == 0) a.model[vi + s] = ok ? m : make_float2(0.0f, 0.0f);
         }
         if (MODE != kDegrid && ok) {
