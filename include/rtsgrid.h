@@ -49,6 +49,7 @@ extern "C" {
 #endif
 
 typedef struct rts_plan_s *rts_plan_t;
+typedef struct rts_graph_s *rts_graph_t;
 
 typedef enum {
   RTS_OK = 0,
@@ -58,7 +59,14 @@ typedef enum {
   RTS_E_UNSUPPORTED = 4,  /* valid request this build does not implement */
 } rts_status;
 
-typedef enum { RTS_PREC_FP32 = 0 } rts_precision;
+typedef enum {
+  RTS_PREC_FP32 = 0,    /* FP32 arithmetic, FP64 tile accumulation (all entry points) */
+  RTS_PREC_BF16X3 = 1   /* rts_grid on the matrix cores: each 16x16-cell tile is the contraction
+                           Av^T diag(wV) Au over its samples with BF16 hi+lo split operands
+                           (hi*hi + hi*lo + lo*hi, FP32 accumulation; ~16 significant bits per
+                           operand).  Tiles are 16 cells.  Degridding and the fused step of such a
+                           plan use the FP32 kernels. */
+} rts_precision;
 
 typedef struct {
   int32_t n_grid;       /* N: grid edge in cells, even, 16 <= N <= 8192                  */
@@ -70,7 +78,8 @@ typedef struct {
   double cell_lambda;   /* du > 0: uv cell size in wavelengths                           */
   double beta;          /* Kaiser-Bessel shape; <= 0 selects 2.34 * W                     */
   int32_t conjugate;    /* 1: also grid conj(w V) at (-u, -v) (rts_grid only)             */
-  int32_t tile;         /* uv tile edge in cells: even, divides N, >= W+1, <= 64; 0 = choose */
+  int32_t tile;         /* uv tile edge in cells: even, divides N, >= W+1, <= 64; 0 = choose
+                           (BF16x3 plans: 0 or 16)                                        */
   int32_t precision;    /* rts_precision                                                 */
   int32_t reserved;     /* must be 0                                                     */
 } rts_params;
@@ -126,6 +135,33 @@ rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *
 rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weights,
                            const float *grid_in, float *model_out, float *grid_out,
                            double *chi2_out, void *stream);
+
+/* One cadence step as a HIP graph: rts_plan_update(uvw_m, weights) followed by
+ * rts_grid_degrid(vis, weights, grid_in -> model_out, grid_out, chi2_out) is
+ * captured once (on a private stream, after the work already queued on `stream`)
+ * and each rts_cadence_graph_launch replays both over whatever the same buffers
+ * hold at launch time, e.g. the next cadence's uvw, weights and visibilities.
+ * All buffers must stay allocated at the same addresses while the graph lives;
+ * the capture contains no allocation, memset or host synchronisation.  The
+ * work-list capacity limit of rts_plan_update applies (rts_plan_info.n_dropped).
+ * Plans with conjugate copies return RTS_E_UNSUPPORTED. */
+rts_status rts_cadence_graph_create(rts_graph_t *out, rts_plan_t plan, const double *uvw_m,
+                                    const float *vis, const float *weights, const float *grid_in,
+                                    float *model_out, float *grid_out, double *chi2_out, void *stream);
+rts_status rts_cadence_graph_launch(rts_graph_t graph, void *stream);
+rts_status rts_cadence_graph_destroy(rts_graph_t graph);   /* NULL is accepted */
+
+/* Tile-size autotuner: builds a plan for every legal tile edge in {16, 32, 64},
+ * times three cadence steps (rts_plan_update + rts_grid_degrid) of each on the
+ * given inputs with HIP events, and returns the fastest in *best_tile.  The
+ * choice is cached per (N, W, OS, C, B, T, conjugate, du) for the process; a
+ * non-NULL ms_out forces a fresh measurement and receives up to `capacity`
+ * per-candidate times (tiles_out the candidates, *n_tried their count).
+ * Allocates scratch for the model and grid outputs; synchronises `stream`. */
+rts_status rts_autotune_tile(const rts_params *params, const double *uvw_m, const double *freq_hz,
+                             const float *weights, const float *vis, const float *grid_in,
+                             void *stream, int32_t *best_tile, float *ms_out, int32_t *tiles_out,
+                             int32_t capacity, int32_t *n_tried);
 
 /* a1 exposed for exact testing: out[c][b][t] = {xs, ys, valid} (int32) where
  * (xs, ys) are the snapped oversampled coordinates floor((u f/(c du) + N/2) OS + 1/2)

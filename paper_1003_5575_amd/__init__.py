@@ -16,7 +16,7 @@ import ctypes
 from . import _lib
 from ._lib import RtsError, RtsParams, RtsPlanInfo  # noqa: F401
 
-__all__ = ["GridPlan", "compute_coords", "RtsError", "library_path", "version", "GridFn", "DegridFn",
+__all__ = ["GridPlan", "CadenceGraph", "autotune_tile", "compute_coords", "RtsError", "library_path", "version", "GridFn", "DegridFn",
            "Chi2Fn", "grid", "degrid", "chi2"]
 
 
@@ -57,8 +57,11 @@ def _check_dev(t, name, dtype, shape=None):
     return t
 
 
+PRECISIONS = {"fp32": 0, "bf16x3": 1}
+
+
 def make_params(n_grid, cell_lambda, support, oversample, n_chan, n_base, n_time, beta=None,
-                conjugate=False, tile=0) -> RtsParams:
+                conjugate=False, tile=0, precision="fp32") -> RtsParams:
     p = RtsParams()
     p.n_grid, p.support, p.oversample = int(n_grid), int(support), int(oversample)
     p.n_chan, p.n_base, p.n_time = int(n_chan), int(n_base), int(n_time)
@@ -66,7 +69,7 @@ def make_params(n_grid, cell_lambda, support, oversample, n_chan, n_base, n_time
     p.beta = float(beta) if beta is not None else 0.0
     p.conjugate = int(bool(conjugate))
     p.tile = int(tile)
-    p.precision = 0
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.reserved = 0
     return p
 
@@ -76,7 +79,7 @@ class GridPlan:
     freq_hz [C] (host sequence), weights [C][B][T] (float32, device; 0 = flagged)."""
 
     def __init__(self, uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversample=8,
-                 beta=None, conjugate=False, tile=0, stream=None):
+                 beta=None, conjugate=False, tile=0, stream=None, precision="fp32"):
         torch = _torch()
         lib = _lib.load()
         _check_dev(uvw, "uvw", torch.float64)
@@ -86,7 +89,8 @@ class GridPlan:
         freq = [float(f) for f in freq_hz]
         C = len(freq)
         _check_dev(weights, "weights", torch.float32, (C, B, T))
-        self.params = make_params(n_grid, cell_lambda, support, oversample, C, B, T, beta, conjugate, tile)
+        self.params = make_params(n_grid, cell_lambda, support, oversample, C, B, T, beta, conjugate, tile,
+                                  precision)
         self.C, self.B, self.T, self.N = C, B, T, int(n_grid)
         self.device = uvw.device
         self._freq = (ctypes.c_double * C)(*freq)
@@ -189,6 +193,10 @@ class GridPlan:
                                                _stream(stream)), "rts_grid_degrid")
         return model_out, grid_out, chi2_out
 
+    def cadence_graph(self, uvw, vis, weights, grid_in, model_out, grid_out, chi2_out, stream=None):
+        """Capture [update(uvw, weights); grid_degrid(...)] once; see CadenceGraph."""
+        return CadenceGraph(self, uvw, vis, weights, grid_in, model_out, grid_out, chi2_out, stream)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.check(_lib.load().rts_plan_destroy(self._h), "rts_plan_destroy")
@@ -205,6 +213,70 @@ class GridPlan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class CadenceGraph:
+    """A captured cadence step (re-plan + fused pass) replayed with one graph launch.
+
+    The tensors passed at capture are the ones every replay reads and writes: copy
+    the next cadence's uvw, weights and visibilities into them, then launch()."""
+
+    def __init__(self, plan, uvw, vis, weights, grid_in, model_out, grid_out, chi2_out, stream=None):
+        torch = _torch()
+        _check_dev(uvw, "uvw", torch.float64, (plan.B, plan.T, 3))
+        _check_dev(vis, "vis", torch.complex64, plan._vis_shape())
+        _check_dev(weights, "weights", torch.float32, plan._vis_shape())
+        _check_dev(grid_in, "grid_in", torch.complex64, plan._grid_shape())
+        _check_dev(grid_out, "grid_out", torch.complex64, plan._grid_shape())
+        if model_out is not None:
+            _check_dev(model_out, "model_out", torch.complex64, plan._vis_shape())
+        if chi2_out is not None:
+            _check_dev(chi2_out, "chi2_out", torch.float64)
+        self._keep = (plan, uvw, vis, weights, grid_in, model_out, grid_out, chi2_out)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().rts_cadence_graph_create(ctypes.byref(h), plan.handle, _ptr(uvw), _ptr(vis),
+                                                        _ptr(weights), _ptr(grid_in), _ptr(model_out),
+                                                        _ptr(grid_out), _ptr(chi2_out), _stream(stream)),
+                   "rts_cadence_graph_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _lib.check(_lib.load().rts_cadence_graph_launch(self._h, _stream(stream)), "rts_cadence_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().rts_cadence_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_tile(uvw, freq_hz, weights, vis, grid_in, n_grid, cell_lambda, support=7, oversample=8,
+                  beta=None, conjugate=False, stream=None, measure=True):
+    """Time each legal tile edge on these inputs; returns (best_tile, {tile: ms})."""
+    torch = _torch()
+    B, T = int(uvw.shape[0]), int(uvw.shape[1])
+    freq = [float(f) for f in freq_hz]
+    C = len(freq)
+    _check_dev(uvw, "uvw", torch.float64, (B, T, 3))
+    _check_dev(weights, "weights", torch.float32, (C, B, T))
+    _check_dev(vis, "vis", torch.complex64, (C, B, T))
+    _check_dev(grid_in, "grid_in", torch.complex64, (C, n_grid, n_grid))
+    p = make_params(n_grid, cell_lambda, support, oversample, C, B, T, beta, conjugate, 0)
+    fr = (ctypes.c_double * C)(*freq)
+    best = ctypes.c_int32()
+    ms = (ctypes.c_float * 8)()
+    tiles = (ctypes.c_int32 * 8)()
+    n = ctypes.c_int32()
+    _lib.check(_lib.load().rts_autotune_tile(ctypes.byref(p), _ptr(uvw), ctypes.cast(fr, ctypes.c_void_p),
+                                             _ptr(weights), _ptr(vis), _ptr(grid_in), _stream(stream),
+                                             ctypes.byref(best), ms if measure else None, tiles, 8,
+                                             ctypes.byref(n)), "rts_autotune_tile")
+    return best.value, {tiles[k]: ms[k] for k in range(n.value)}
 
 
 def compute_coords(uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversample=8, stream=None):

@@ -63,6 +63,21 @@ double kaiser_bessel(double t, int W, double beta) {
 
 bool aligned(const void *p, size_t n) { return ((uintptr_t)p % n) == 0; }
 
+// IEEE binary32 -> bfloat16 bits, round to nearest even (finite inputs).
+uint16_t bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 rts_status validate(const rts_params *p) {
   RTS_REQUIRE(p != nullptr, "params is NULL");
   RTS_REQUIRE(p->n_grid >= 16 && p->n_grid <= kMaxN && p->n_grid % 2 == 0,
@@ -76,12 +91,16 @@ rts_status validate(const rts_params *p) {
   RTS_REQUIRE(std::isfinite(p->cell_lambda) && p->cell_lambda > 0.0, "cell_lambda must be > 0");
   RTS_REQUIRE(std::isfinite(p->beta), "beta must be finite");
   RTS_REQUIRE(p->conjugate == 0 || p->conjugate == 1, "conjugate must be 0 or 1");
-  RTS_REQUIRE(p->precision == RTS_PREC_FP32, "precision %d is not available", p->precision);
+  RTS_REQUIRE(p->precision == RTS_PREC_FP32 || p->precision == RTS_PREC_BF16X3, "precision %d is not available",
+              p->precision);
   RTS_REQUIRE(p->reserved == 0, "reserved must be 0");
   const int64_t n = (int64_t)p->n_chan * p->n_base * p->n_time * (1 + p->conjugate);
   RTS_REQUIRE(n < ((int64_t)1 << 31), "n_chan*n_base*n_time*(1+conjugate) must be < 2^31");
   RTS_REQUIRE(p->n_grid >= p->support + 2, "n_grid must be at least support + 2");
-  if (p->tile != 0) {
+  if (p->precision == RTS_PREC_BF16X3) {
+    RTS_REQUIRE(p->tile == 0 || p->tile == 16, "BF16x3 plans use 16-cell tiles (got tile %d)", p->tile);
+    RTS_REQUIRE(p->n_grid % 16 == 0, "BF16x3 plans need n_grid divisible by 16");
+  } else if (p->tile != 0) {
     RTS_REQUIRE(p->tile >= p->support + 1 && p->tile <= kMaxTile && p->tile % 2 == 0 &&
                     p->n_grid % p->tile == 0,
                 "tile must be even, divide n_grid, and lie in [support+1, %d] (got %d)", kMaxTile,
@@ -119,17 +138,28 @@ void fill_tables(Plan &P) {
   // of window columns 0..W for a sample whose cell is d in {0,1} past the window's
   // first tap position, with phase row p.
   P.tabE.assign((size_t)2 * OS * P.WNP, 0.0f);
+  P.tab_hi.assign((size_t)2 * OS * P.WNP, 0);
+  P.tab_lo.assign((size_t)2 * OS * P.WNP, 0);
   for (int d = 0; d < 2; ++d)
     for (int p = 0; p < OS; ++p)
       for (int i = 0; i < P.WN; ++i) {
         const int j = i - d;
-        if (j >= 0 && j < W) P.tabE[(size_t)(d * OS + p) * P.WNP + i] = P.tab[(size_t)p * W + j];
+        if (j >= 0 && j < W) {
+          const size_t e = (size_t)(d * OS + p) * P.WNP + i;
+          P.tabE[e] = P.tab[(size_t)p * W + j];
+          // BF16 hi + lo split of the FP64 kernel value, for the matrix-core path
+          const double k = kaiser_bessel((double)(j - P.h_lo) - (double)(P.r0 + p) / OS, W, P.beta);
+          P.tab_hi[e] = bf16_bits((float)k);
+          P.tab_lo[e] = bf16_bits((float)(k - (double)bf16_value(P.tab_hi[e])));
+        }
       }
 }
 
 void free_plan(Plan *P) {
   if (!P) return;
   hipFree(P->d_tabE);
+  hipFree(P->d_tab_hi);
+  hipFree(P->d_tab_lo);
   hipFree(P->d_scale);
   hipFree(P->d_coords);
   hipFree(P->d_list);
@@ -249,13 +279,22 @@ TileArgs tile_args(const Plan &P) {
   a.list_cap = P.list_cap;
   a.N = P.N; a.tile = P.tile; a.nT = P.nT; a.nT2 = P.nT2; a.nkeys = (int)P.nkeys;
   a.B = P.B; a.T = P.T; a.ncopy = P.ncopy;
-  a.OS2 = 2 * P.OS; a.WNP = P.WNP;
+  a.OS2 = 2 * P.OS; a.WNP = P.WNP; a.WN = P.WN;
+  a.vec = 0;
   return a;
 }
 
 template <class T>
 hipError_t dalloc(T **p, size_t n) {
   return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+// Whole-track segments can use vector loads/stores when every track is exactly
+// one segment's length and the per-sample arrays are 16-byte aligned.
+int vector_ok(const Plan &P, const void *vis, const void *w, const void *model) {
+  if (P.T != P.seg_max || (P.seg_max != 4 && P.seg_max != 8)) return 0;
+  if ((vis && !aligned(vis, 16)) || (w && !aligned(w, 16)) || (model && !aligned(model, 16))) return 0;
+  return 1;
 }
 
 rts_status check_plan(rts_plan_t plan) {
@@ -274,10 +313,20 @@ bool tile_supported(int W, int seg_max) {
 
 hipError_t launch_tile(int mode, const Plan &P, const TileArgs &a, hipStream_t s) {
   switch (mode) {
-    case kGrid: return launch_tile_mode<kGrid>(P, a, s);
-    case kDegrid: return launch_tile_mode<kDegrid>(P, a, s);
-    default: return launch_tile_mode<kFused>(P, a, s);
+    case kGrid: return launch_tile_mode<kGrid>(P, a, s, false);
+    case kDegrid: return launch_tile_mode<kDegrid>(P, a, s, false);
+    default: return launch_tile_mode<kFused>(P, a, s, false);
   }
+}
+
+hipError_t prepare_tile_kernels(const Plan &P) {
+  TileArgs a{};
+  a.OS2 = 2 * P.OS;
+  a.WNP = P.WNP;
+  hipError_t e = launch_tile_mode<kGrid>(P, a, nullptr, true);
+  if (e == hipSuccess) e = launch_tile_mode<kDegrid>(P, a, nullptr, true);
+  if (e == hipSuccess) e = launch_tile_mode<kFused>(P, a, nullptr, true);
+  return e;
 }
 
 }  // namespace rts
@@ -315,7 +364,8 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   P->r0 = (P->W & 1) ? -(P->OS / 2) : 0;
   P->h_lo = (P->W & 1) ? (P->W - 1) / 2 : P->W / 2 - 1;
   P->beta = params->beta > 0.0 ? params->beta : 2.34 * P->W;
-  P->tile = params->tile ? params->tile : choose_tile(P->N, P->WN);
+  P->precision = params->precision;
+  P->tile = params->precision == RTS_PREC_BF16X3 ? 16 : (params->tile ? params->tile : choose_tile(P->N, P->WN));
   if (P->tile == 0) {
     set_error("no legal tile size for n_grid=%d support=%d", P->N, P->W);
     return RTS_E_UNSUPPORTED;
@@ -331,6 +381,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   }
   fill_tables(*P);
   RTS_HIP(hipGetDevice(&P->device));
+  RTS_HIP(prepare_tile_kernels(*P));
   hipStream_t s = (hipStream_t)stream;
 
   const int64_t nsamp = (int64_t)P->C * P->B * P->T;
@@ -338,6 +389,8 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   const int64_t nscan = P->nbx > 0 ? P->nkeys * P->nbx : P->nkeys;
   P->scan_blocks = (nscan + 4095) / 4096;
   RTS_HIP(dalloc(&P->d_tabE, P->tabE.size()));
+  RTS_HIP(dalloc(&P->d_tab_hi, P->tab_hi.size()));
+  RTS_HIP(dalloc(&P->d_tab_lo, P->tab_lo.size()));
   RTS_HIP(dalloc(&P->d_scale, (size_t)P->C));
   RTS_HIP(dalloc(&P->d_coords, (size_t)nsamp * P->ncopy));
   RTS_HIP(dalloc(&P->d_tile_off, (size_t)P->nkeys + 1));
@@ -357,6 +410,8 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
                          hipMemcpyHostToDevice, s));
   RTS_HIP(hipMemcpyAsync(P->d_scale, scale.data(), scale.size() * sizeof(double),
                          hipMemcpyHostToDevice, s));
+  RTS_HIP(hipMemcpyAsync(P->d_tab_hi, P->tab_hi.data(), P->tab_hi.size() * 2, hipMemcpyHostToDevice, s));
+  RTS_HIP(hipMemcpyAsync(P->d_tab_lo, P->tab_lo.data(), P->tab_lo.size() * 2, hipMemcpyHostToDevice, s));
   RTS_HIP(launch_fill_u32(P->d_cursor, P->nkeys, 0u, s));
   RTS_HIP(launch_fill_u32((uint32_t *)P->d_stats, 16, 0u, s));
 
@@ -423,7 +478,11 @@ rts_status rts_grid(rts_plan_t plan, const float *vis, const float *weights, flo
   a.vis = (const float2 *)vis;
   a.w = weights;
   a.gout = (float2 *)grid;
-  RTS_HIP(launch_tile(kGrid, *plan, a, (hipStream_t)stream));
+  a.vec = vector_ok(*plan, vis, weights, nullptr);
+  if (plan->precision == RTS_PREC_BF16X3)
+    RTS_HIP(launch_grid_mfma(*plan, a, (hipStream_t)stream));
+  else
+    RTS_HIP(launch_tile(kGrid, *plan, a, (hipStream_t)stream));
   return RTS_OK;
 }
 
@@ -434,6 +493,7 @@ rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *
   TileArgs a = tile_args(*plan);
   a.gin = (const float2 *)grid;
   a.model = (float2 *)vis_out;
+  a.vec = vector_ok(*plan, nullptr, nullptr, vis_out);
   RTS_HIP(launch_tile(kDegrid, *plan, a, (hipStream_t)stream));
   return RTS_OK;
 }
@@ -460,6 +520,7 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
   a.gout = (float2 *)grid_out;
   a.model = (float2 *)model_out;
   a.write_model = model_out != nullptr;
+  a.vec = vector_ok(*plan, vis, weights, model_out);
   hipStream_t s = (hipStream_t)stream;
   RTS_HIP(launch_tile(kFused, *plan, a, s));
   if (chi2_out) RTS_HIP(launch_chi2_reduce(plan->d_chi2_part, plan->nkeys, chi2_out, s));

@@ -82,10 +82,21 @@ struct TileArgs {
   int64_t list_cap;          // listings at or beyond this index are ignored
   int N, tile, nT, nT2, nkeys;
   int B, T, ncopy;
-  int OS2, WNP;
+  int OS2, WNP, WN;
   int write_model;
+  int vec;                   // whole-track segments may use 16-byte vector loads and stores
 };
 
+}  // namespace rts
+
+namespace rts {
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs, each with its
+// own L2.  Remap so that every XCD walks one contiguous range of tiles: a tile's
+// neighbours (whose windows overlap it) then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+  const int q = n >> 3, r = n & 7, xcd = bid & 7, slot = bid >> 3;
+  return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
 }  // namespace rts
 
 // Plan state behind the opaque rts_plan_t handle.
@@ -98,7 +109,11 @@ struct rts_plan_s {
   int device = 0;
   std::vector<float> tab;    // [OS][W]
   std::vector<float> tabE;   // [2*OS][WNP]
+  std::vector<uint16_t> tab_hi, tab_lo;   // [2*OS][WNP] bf16 bits: hi = bf16(k), lo = bf16(k - hi)
+  int precision = 0;
   float *d_tabE = nullptr;
+  uint16_t *d_tab_hi = nullptr;
+  uint16_t *d_tab_lo = nullptr;
   double *d_scale = nullptr;
   uint16_t *d_coords = nullptr;
   uint2 *d_list = nullptr;
@@ -142,8 +157,10 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 
 // tile kernels (tile_*.hip)
 template <int MODE>
-hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s);
+hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s, bool prepare);
 hipError_t launch_tile(int mode, const Plan &P, const TileArgs &a, hipStream_t s);
+hipError_t prepare_tile_kernels(const Plan &P);
+hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s);
 bool tile_supported(int W, int seg_max);
 
 }  // namespace rts

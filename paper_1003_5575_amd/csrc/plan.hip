@@ -770,20 +770,41 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total)
 
 __global__ __launch_bounds__(kBlock) void k_scan_local(const uint32_t *in, uint32_t *out,
                                                        uint32_t *bsum, int64_t n) {
+  // Each thread owns 16 consecutive counts, read and written as four 16-byte
+  // vectors when the block is full (the tail block falls back to scalars).
   const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + (int64_t)threadIdx.x * kScanPerThread;
   uint32_t v[kScanPerThread];
+  const bool full = (int64_t)(blockIdx.x + 1) * kScanPerBlock <= n;
+  if (full) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(in + base);
+#pragma unroll
+    for (int h = 0; h < kScanPerThread / 4; ++h) {
+      const uint4 x = p[h];
+      v[4 * h] = x.x; v[4 * h + 1] = x.y; v[4 * h + 2] = x.z; v[4 * h + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i) v[i] = (base + i < n) ? in[base + i] : 0u;
+  }
   uint32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanPerThread; ++i) {
-    v[i] = (base + i < n) ? in[base + i] : 0u;
-    s += v[i];
-  }
+  for (int i = 0; i < kScanPerThread; ++i) s += v[i];
   uint32_t total;
   uint32_t pre = block_excl_scan(s, total);
 #pragma unroll
   for (int i = 0; i < kScanPerThread; ++i) {
-    if (base + i < n) out[base + i] = pre;
-    pre += v[i];
+    const uint32_t x = v[i];
+    v[i] = pre;
+    pre += x;
+  }
+  if (full) {
+    uint4 *q = reinterpret_cast<uint4 *>(out + base);
+#pragma unroll
+    for (int h = 0; h < kScanPerThread / 4; ++h) q[h] = make_uint4(v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanPerThread; ++i)
+      if (base + i < n) out[base + i] = v[i];
   }
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }

@@ -6,12 +6,15 @@
 
 namespace rts {
 
+// With prepare set, only raise the kernel's dynamic-LDS limit (done once, when a
+// plan is built, so that launches stay capturable); otherwise launch.
 #define RTS_TILE_LAUNCH(WNV, SM, BLK, GRP)                                                     \
   {                                                                                            \
-    if (lds > 65536) {                                                                         \
-      hipError_t e = hipFuncSetAttribute((const void *)k_tile<WNV, SM, MODE, BLK, GRP>,        \
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-      if (e != hipSuccess) return e;                                                           \
+    if (prepare) {                                                                             \
+      if (lds > 65536)                                                                         \
+        return hipFuncSetAttribute((const void *)k_tile<WNV, SM, MODE, BLK, GRP>,              \
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);      \
+      return hipSuccess;                                                                       \
     }                                                                                          \
     hipLaunchKernelGGL((k_tile<WNV, SM, MODE, BLK, GRP>), dim3(nblk), dim3(BLK), lds, s, a);  \
   }
@@ -26,7 +29,7 @@ namespace rts {
     break;
 
 template <int MODE>
-hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s) {
+hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s, bool prepare) {
   const unsigned nblk = (unsigned)P.nkeys;
   size_t lds = (size_t)a.OS2 * a.WNP * sizeof(float);
   if (MODE != kDegrid) lds += (size_t)2 * P.tile * P.tile * sizeof(double);

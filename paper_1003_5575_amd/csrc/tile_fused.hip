@@ -2,5 +2,5 @@
 #include "tile_dispatch.h"
 
 namespace rts {
-template hipError_t launch_tile_mode<kFused>(const Plan &, const TileArgs &, hipStream_t);
+template hipError_t launch_tile_mode<kFused>(const Plan &, const TileArgs &, hipStream_t, bool);
 }  // namespace rts

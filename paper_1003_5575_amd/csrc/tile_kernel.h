@@ -21,20 +21,16 @@
 
 namespace rts {
 
-// Consecutive workgroups are dispatched round-robin over the 8 XCDs, each with its
-// own L2.  Remap so that every XCD walks one contiguous range of tiles: a tile's
-// neighbours (whose windows overlap it) then share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int bid, int n) {
-  const int q = n >> 3, r = n & 7, xcd = bid & 7, slot = bid >> 3;
-  return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-}
 
 // Lanes per segment and window columns per lane.  A group of GROUP adjacent
 // lanes shares one segment; lane q of the group owns window columns q*CPL ..
 // q*CPL+CPL-1, holds those columns of the G_in window and of the accumulated
 // update in registers, and the degridded value of each sample is the sum of the
 // group's partial sums (butterfly steps inside the group of lanes).
-// Minimum waves per SIMD the register allocation of the tile kernel targets.
+// Minimum waves per SIMD the register allocation of the tile kernel targets for
+// small tiles (128-thread workgroups).  64-cell tiles hold a 64 KiB FP64
+// accumulator, so at most two of their 256-thread workgroups share a CU (two
+// waves per SIMD) and the kernel may use up to 256 registers.
 #ifndef RTS_TILE_WAVES
 #define RTS_TILE_WAVES 4
 #endif
@@ -49,7 +45,7 @@ __device__ __forceinline__ float quad_xor2(float v) {
 }
 
 template <int WN, int SMAX, int MODE, int BLOCK, int GROUP>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 4 ? RTS_TILE_WAVES : 2))) void k_tile(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 4 && BLOCK < 256 ? RTS_TILE_WAVES : 2))) void k_tile(
     TileArgs a) {
   // GROUP lanes (2 or 4) share a segment; each owns CPL window columns.
   constexpr int kGroup = GROUP;
@@ -111,16 +107,48 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 
     uint32_t cws[SMAX];
     float2 vs[SMAX];
     float ws[SMAX];
+    // A whole track that is one segment starts SMAX-aligned: its coordinates,
+    // visibilities and weights are loaded with 16-byte (or 8-byte) vector loads.
+    const bool vec = a.vec && nt == SMAX;
+    if (vec) {
+      if (SMAX == 8) {
+        const uint4 c4 = *reinterpret_cast<const uint4 *>(a.coords + ci);
+        cws[0] = c4.x & 0xFFFFu; cws[1 % SMAX] = c4.x >> 16;
+        cws[2 % SMAX] = c4.y & 0xFFFFu; cws[3 % SMAX] = c4.y >> 16;
+        cws[4 % SMAX] = c4.z & 0xFFFFu; cws[5 % SMAX] = c4.z >> 16;
+        cws[6 % SMAX] = c4.w & 0xFFFFu; cws[7 % SMAX] = c4.w >> 16;
+      } else {
+        const uint2 c2 = *reinterpret_cast<const uint2 *>(a.coords + ci);
+        cws[0] = c2.x & 0xFFFFu; cws[1 % SMAX] = c2.x >> 16;
+        cws[2 % SMAX] = c2.y & 0xFFFFu; cws[3 % SMAX] = c2.y >> 16;
+      }
+      if (MODE != kDegrid) {
+        const float4 *v4 = reinterpret_cast<const float4 *>(a.vis + vi);
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      cws[s] = 0u;
-      vs[s] = make_float2(0.0f, 0.0f);
-      ws[s] = 0.0f;
-      if (s < nt) {
-        cws[s] = a.coords[ci + s];
-        if (MODE != kDegrid) {
-          vs[s] = a.vis[vi + s];
-          ws[s] = a.w[vi + s];
+        for (int h = 0; h < SMAX / 2; ++h) {
+          const float4 t4 = v4[h];
+          vs[2 * h] = make_float2(t4.x, t4.y);
+          vs[2 * h + 1] = make_float2(t4.z, t4.w);
+        }
+        const float4 *w4 = reinterpret_cast<const float4 *>(a.w + vi);
+#pragma unroll
+        for (int h = 0; h < SMAX / 4; ++h) {
+          const float4 t4 = w4[h];
+          ws[4 * h] = t4.x; ws[4 * h + 1] = t4.y; ws[4 * h + 2] = t4.z; ws[4 * h + 3] = t4.w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) {
+        cws[s] = 0u;
+        vs[s] = make_float2(0.0f, 0.0f);
+        ws[s] = 0.0f;
+        if (s < nt) {
+          cws[s] = a.coords[ci + s];
+          if (MODE != kDegrid) {
+            vs[s] = a.vis[vi + s];
+            ws[s] = a.w[vi + s];
+          }
         }
       }
     }
@@ -144,6 +172,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 
     }
 
     float chi2_seg = 0.0f;   // this segment's sum of w |r|^2 (SMAX terms, FP32)
+    // With the 256-register budget the segment's model values are kept and
+    // stored together after the sample loop; otherwise each is stored at once.
+    constexpr bool kBufModel = BLOCK >= 256;
+    float2 mv[SMAX];
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
       if (s < nt) {
@@ -195,7 +227,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 
             m.x += quad_xor2(m.x);
             m.y += quad_xor2(m.y);
           }
-          if (put_model && q == 0) a.model[vi + s] = ok ? m : make_float2(0.0f, 0.0f);
+          mv[s] = ok ? m : make_float2(0.0f, 0.0f);
+          if (!kBufModel && put_model && q == 0) a.model[vi + s] = mv[s];
         }
         if (MODE != kDegrid && ok) {
           float2 v = vs[s];
@@ -225,11 +258,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 
     }
 
     if (MODE == kFused && home && q == 0) chi2 += (double)chi2_seg;
+    if (kBufModel && MODE != kGrid && put_model && q == 0) {
+      if (vec) {
+        float4 *m4 = reinterpret_cast<float4 *>(a.model + vi);
+#pragma unroll
+        for (int h = 0; h < SMAX / 2; ++h) m4[h] = make_float4(mv[2 * h].x, mv[2 * h].y, mv[2 * h + 1].x, mv[2 * h + 1].y);
+      } else {
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+          if (s < nt) a.model[vi + s] = mv[s];
+      }
+    }
     if (MODE != kDegrid) {
       // Add this lane's window columns to the tile accumulator.  Windows entirely
       // inside the tile (most of them) skip the per-cell bounds checks.
       const int lx = X0 + col0 - x0, ly = Y0 - y0;
-      const bool inside = (unsigned)(X0 - x0) <= (unsigned)(T - WN) && (unsigned)ly <= (unsigned)(T - WN);
+      const bool inside = T >= WN && (unsigned)(X0 - x0) <= (unsigned)(T - WN) && (unsigned)ly <= (unsigned)(T - WN);
       double *row = acc + 2 * (ly * T + lx);      // dereferenced only inside the tile
       if (inside) {
 #pragma unroll
