@@ -68,6 +68,14 @@ typedef enum {
                            plan use the FP32 kernels. */
 } rts_precision;
 
+typedef enum {
+  RTS_SCHEDULE_AUTO = 0,        /* the library's choice (currently RTS_SCHEDULE_TILES)          */
+  RTS_SCHEDULE_TILES = 1,       /* one workgroup per (channel, tile), XCD-grouped               */
+  RTS_SCHEDULE_PERSISTENT = 2   /* two to six workgroups per compute unit pull tiles from eight
+                                   per-XCD queues in longest-first order, which the plan builds
+                                   (load balance for skewed uv coverage; not in the paper)     */
+} rts_schedule;
+
 typedef struct {
   int32_t n_grid;       /* N: grid edge in cells, even, 16 <= N <= 8192                  */
   int32_t support;      /* W: taps per axis, 2 <= W <= 16                                */
@@ -81,7 +89,7 @@ typedef struct {
   int32_t tile;         /* uv tile edge in cells: even, divides N, >= W+1, <= 64; 0 = choose
                            (BF16x3 plans: 0 or 16)                                        */
   int32_t precision;    /* rts_precision                                                 */
-  int32_t reserved;     /* must be 0                                                     */
+  int32_t schedule;     /* rts_schedule: how the FP32 tile kernels are launched           */
 } rts_params;
 
 typedef struct {

@@ -58,10 +58,11 @@ def _check_dev(t, name, dtype, shape=None):
 
 
 PRECISIONS = {"fp32": 0, "bf16x3": 1}
+SCHEDULES = {"auto": 0, "tiles": 1, "persistent": 2}
 
 
 def make_params(n_grid, cell_lambda, support, oversample, n_chan, n_base, n_time, beta=None,
-                conjugate=False, tile=0, precision="fp32") -> RtsParams:
+                conjugate=False, tile=0, precision="fp32", schedule="auto") -> RtsParams:
     p = RtsParams()
     p.n_grid, p.support, p.oversample = int(n_grid), int(support), int(oversample)
     p.n_chan, p.n_base, p.n_time = int(n_chan), int(n_base), int(n_time)
@@ -70,7 +71,7 @@ def make_params(n_grid, cell_lambda, support, oversample, n_chan, n_base, n_time
     p.conjugate = int(bool(conjugate))
     p.tile = int(tile)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    p.reserved = 0
+    p.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     return p
 
 
@@ -79,7 +80,7 @@ class GridPlan:
     freq_hz [C] (host sequence), weights [C][B][T] (float32, device; 0 = flagged)."""
 
     def __init__(self, uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversample=8,
-                 beta=None, conjugate=False, tile=0, stream=None, precision="fp32"):
+                 beta=None, conjugate=False, tile=0, stream=None, precision="fp32", schedule="auto"):
         torch = _torch()
         lib = _lib.load()
         _check_dev(uvw, "uvw", torch.float64)
@@ -90,7 +91,7 @@ class GridPlan:
         C = len(freq)
         _check_dev(weights, "weights", torch.float32, (C, B, T))
         self.params = make_params(n_grid, cell_lambda, support, oversample, C, B, T, beta, conjugate, tile,
-                                  precision)
+                                  precision, schedule)
         self.C, self.B, self.T, self.N = C, B, T, int(n_grid)
         self.device = uvw.device
         self._freq = (ctypes.c_double * C)(*freq)

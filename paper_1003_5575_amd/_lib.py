@@ -27,7 +27,7 @@ class RtsParams(ctypes.Structure):
         ("n_chan", ctypes.c_int32), ("n_base", ctypes.c_int32), ("n_time", ctypes.c_int32),
         ("cell_lambda", ctypes.c_double), ("beta", ctypes.c_double),
         ("conjugate", ctypes.c_int32), ("tile", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
     ]
 
 

@@ -93,7 +93,8 @@ rts_status validate(const rts_params *p) {
   RTS_REQUIRE(p->conjugate == 0 || p->conjugate == 1, "conjugate must be 0 or 1");
   RTS_REQUIRE(p->precision == RTS_PREC_FP32 || p->precision == RTS_PREC_BF16X3, "precision %d is not available",
               p->precision);
-  RTS_REQUIRE(p->reserved == 0, "reserved must be 0");
+  RTS_REQUIRE(p->schedule >= RTS_SCHEDULE_AUTO && p->schedule <= RTS_SCHEDULE_PERSISTENT,
+              "schedule %d is not available", p->schedule);
   const int64_t n = (int64_t)p->n_chan * p->n_base * p->n_time * (1 + p->conjugate);
   RTS_REQUIRE(n < ((int64_t)1 << 31), "n_chan*n_base*n_time*(1+conjugate) must be < 2^31");
   RTS_REQUIRE(p->n_grid >= p->support + 2, "n_grid must be at least support + 2");
@@ -169,6 +170,8 @@ void free_plan(Plan *P) {
   hipFree(P->d_hist);
   hipFree(P->d_offs);
   hipFree(P->d_desc);
+  hipFree(P->d_order);
+  hipFree(P->d_lpt);
   hipFree(P->d_stats);
   hipFree(P->d_chi2_part);
   delete P;
@@ -281,6 +284,8 @@ TileArgs tile_args(const Plan &P) {
   a.B = P.B; a.T = P.T; a.ncopy = P.ncopy;
   a.OS2 = 2 * P.OS; a.WNP = P.WNP; a.WN = P.WN;
   a.vec = 0;
+  a.order = P.d_order;
+  a.queue = P.d_lpt ? P.d_lpt + kLptQueue : nullptr;
   return a;
 }
 
@@ -381,6 +386,8 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   }
   fill_tables(*P);
   RTS_HIP(hipGetDevice(&P->device));
+  RTS_HIP(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device));
+  P->schedule = params->schedule == RTS_SCHEDULE_AUTO ? RTS_SCHEDULE_TILES : params->schedule;
   RTS_HIP(prepare_tile_kernels(*P));
   hipStream_t s = (hipStream_t)stream;
 
@@ -402,6 +409,10 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
     RTS_HIP(dalloc(&P->d_hist, (size_t)nscan));
     RTS_HIP(dalloc(&P->d_offs, (size_t)nscan + 1));
     RTS_HIP(dalloc(&P->d_desc, (size_t)P->C * P->ncopy * P->B));
+  }
+  if (P->schedule == RTS_SCHEDULE_PERSISTENT) {
+    RTS_HIP(dalloc(&P->d_order, (size_t)P->nkeys));
+    RTS_HIP(dalloc(&P->d_lpt, (size_t)kLptWords));
   }
 
   std::vector<double> scale(P->C);
@@ -434,6 +445,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   pa.list = P->d_list;
   pa.list_cap = P->list_cap;
   RTS_HIP(launch_plan_scatter(pa, s));
+  if (P->d_order) RTS_HIP(launch_lpt_order(P->d_tile_off, P->nkeys, P->d_lpt, P->d_order, s));
 
   rts_plan_info &I = P->info;
   I.n_samples = nsamp;
@@ -448,7 +460,8 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   I.workspace_bytes = (int64_t)(P->tabE.size() * 4 + P->C * 8 + nsamp * P->ncopy * 2 +
                                 (P->nkeys + 1) * 4 + P->nkeys * 4 + (P->scan_blocks + 1) * 4 + 64 +
                                 (P->nbx > 0 ? (2 * nscan + 1) * 4 + (int64_t)P->C * P->ncopy * P->B * 4 : 0) +
-                                P->nkeys * 8 + P->list_cap * 8);
+                                P->nkeys * 8 + P->list_cap * 8 +
+                                (P->d_order ? P->nkeys * 4 + kLptWords * 4 : 0));
   *out = P.release();
   return RTS_OK;
 }
@@ -464,6 +477,7 @@ rts_status rts_plan_update(rts_plan_t plan, const double *uvw_m, const float *we
   RTS_HIP(launch_plan_count(pa, s));
   RTS_HIP(scan_counts(*plan, s));
   RTS_HIP(launch_plan_scatter(pa, s));
+  if (plan->d_order) RTS_HIP(launch_lpt_order(plan->d_tile_off, plan->nkeys, plan->d_lpt, plan->d_order, s));
   plan->stats_pending = true;
   return RTS_OK;
 }

@@ -85,6 +85,8 @@ struct TileArgs {
   int OS2, WNP, WN;
   int write_model;
   int vec;                   // whole-track segments may use 16-byte vector loads and stores
+  const uint32_t *order;     // persistent launch: tiles in per-XCD longest-first order
+  uint32_t *queue;           // persistent launch: 8 queue counters (zeroed before launch)
 };
 
 }  // namespace rts
@@ -107,6 +109,7 @@ struct rts_plan_s {
   double beta = 0.0;
   int64_t nkeys = 0;
   int device = 0;
+  int n_cu = 256;                  // compute units of the plan's device
   std::vector<float> tab;    // [OS][W]
   std::vector<float> tabE;   // [2*OS][WNP]
   std::vector<uint16_t> tab_hi, tab_lo;   // [2*OS][WNP] bf16 bits: hi = bf16(k), lo = bf16(k - hi)
@@ -123,6 +126,9 @@ struct rts_plan_s {
   uint32_t *d_hist = nullptr;     // chunked sort counts [nkeys][nbx]
   uint32_t *d_offs = nullptr;     // chunked sort offsets [nkeys][nbx] + 1
   uint32_t *d_desc = nullptr;     // chunked sort per-track descriptors [C][ncopy][B]
+  uint32_t *d_order = nullptr;    // tiles in per-XCD longest-first order [nkeys]
+  uint32_t *d_lpt = nullptr;      // LPT bucket counts, offsets, scan scratch, queues
+  int schedule = 0;               // rts_schedule in effect
   int nbx = 0;
   int64_t chunk = 0;
   int cg = 1;                     // chunked sort: channels per workgroup
@@ -161,6 +167,16 @@ hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s, boo
 hipError_t launch_tile(int mode, const Plan &P, const TileArgs &a, hipStream_t s);
 hipError_t prepare_tile_kernels(const Plan &P);
 hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s);
+hipError_t launch_lpt_order(const uint32_t *tile_off, int64_t nkeys, uint32_t *lpt, uint32_t *order, hipStream_t s);
+// Longest-first tile order for the persistent launch: tiles are bucketed by their
+// work-list length (clamped to kLptBins-1) within each eighth of the tile range.
+// Workspace layout (uint32 words): bucket counts, then their exclusive scan
+// (8*kLptBins+1 words), scan block sums, and the eight queue counters.
+constexpr int kLptBins = 1024;
+constexpr int64_t kLptOff = 8 * kLptBins;
+constexpr int64_t kLptTmp = 16 * kLptBins + 8;
+constexpr int64_t kLptQueue = kLptTmp + 8;
+constexpr int64_t kLptWords = kLptQueue + 8;
 bool tile_supported(int W, int seg_max);
 
 }  // namespace rts

@@ -737,6 +737,29 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
   }
 }
 
+// Longest-first tile order per XCD range (persistent launch): tiles are bucketed by
+// their work-list length (clamped to kLptBins-1), longest bucket first, within the
+// eighth of the tile range each XCD owns.
+__global__ __launch_bounds__(kBlock) void k_lpt_count(const uint32_t *tile_off, int64_t nkeys, uint32_t *cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nkeys) return;
+  const int64_t per = (nkeys + 7) / 8;
+  const uint32_t n = tile_off[k + 1] - tile_off[k];
+  const int bin = kLptBins - 1 - (int)min(n, (uint32_t)(kLptBins - 1));
+  atomicAdd(&cnt[(k / per) * kLptBins + bin], 1u);
+}
+
+__global__ __launch_bounds__(kBlock) void k_lpt_scatter(const uint32_t *tile_off, int64_t nkeys, uint32_t *cursor,
+                                                        uint32_t *order) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nkeys) return;
+  const int64_t per = (nkeys + 7) / 8;
+  const uint32_t n = tile_off[k + 1] - tile_off[k];
+  const int bin = kLptBins - 1 - (int)min(n, (uint32_t)(kLptBins - 1));
+  const uint32_t pos = atomicAdd(&cursor[(k / per) * kLptBins + bin], 1u);
+  order[pos] = (uint32_t)k;
+}
+
 // tile_off[key] = offs[key * nbx] (the first slot of the key), tile_off[nkeys] = total.
 __global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t *offs, int64_t nbx, int64_t nkeys,
                                                          uint32_t *tile_off) {
@@ -947,6 +970,19 @@ hipError_t launch_tile_offsets(const uint32_t *offs, int64_t nbx, int64_t nkeys,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((nkeys + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                      offs, nbx, nkeys, tile_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_lpt_order(const uint32_t *tile_off, int64_t nkeys, uint32_t *lpt, uint32_t *order,
+                            hipStream_t s) {
+  uint32_t *cnt = lpt, *off = lpt + kLptOff, *tmp = lpt + kLptTmp;
+  hipError_t e = launch_fill_u32(cnt, 8 * kLptBins, 0u, s);
+  if (e != hipSuccess) return e;
+  const unsigned nb = (unsigned)((nkeys + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_lpt_count, dim3(nb), dim3(kBlock), 0, s, tile_off, nkeys, cnt);
+  e = launch_scan(cnt, off, cnt, tmp, 8 * kLptBins, s);   // cnt becomes the cursors
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lpt_scatter, dim3(nb), dim3(kBlock), 0, s, tile_off, nkeys, cnt, order);
   return hipGetLastError();
 }
 

@@ -11,12 +11,22 @@ namespace rts {
 #define RTS_TILE_LAUNCH(WNV, SM, BLK, GRP)                                                     \
   {                                                                                            \
     if (prepare) {                                                                             \
-      if (lds > 65536)                                                                         \
-        return hipFuncSetAttribute((const void *)k_tile<WNV, SM, MODE, BLK, GRP>,              \
+      if (lds > 65536) {                                                                       \
+        hipError_t e = hipFuncSetAttribute((const void *)k_tile<WNV, SM, MODE, BLK, GRP>,      \
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        if (e != hipSuccess) return e;                                                         \
+        return hipFuncSetAttribute((const void *)k_tile_persistent<WNV, SM, MODE, BLK, GRP>,   \
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);      \
+      }                                                                                        \
       return hipSuccess;                                                                       \
     }                                                                                          \
-    hipLaunchKernelGGL((k_tile<WNV, SM, MODE, BLK, GRP>), dim3(nblk), dim3(BLK), lds, s, a);  \
+    if (persistent) {                                                                          \
+      hipError_t e = launch_fill_u32(a.queue, 8, 0u, s);                                       \
+      if (e != hipSuccess) return e;                                                           \
+      hipLaunchKernelGGL((k_tile_persistent<WNV, SM, MODE, BLK, GRP>), dim3(npers), dim3(BLK), lds, s, a); \
+    } else {                                                                                   \
+      hipLaunchKernelGGL((k_tile<WNV, SM, MODE, BLK, GRP>), dim3(nblk), dim3(BLK), lds, s, a);  \
+    }                                                                                          \
   }
 #ifndef RTS_SMALL_W_GROUP
 #define RTS_SMALL_W_GROUP 4
@@ -31,6 +41,11 @@ namespace rts {
 template <int MODE>
 hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s, bool prepare) {
   const unsigned nblk = (unsigned)P.nkeys;
+  // Persistent launch: as many workgroups as fit on the GPU at once (LDS decides
+  // for large tiles), never more than there are tiles.
+  const bool persistent = P.schedule == RTS_SCHEDULE_PERSISTENT && a.order && a.queue;
+  const int per_cu = (P.tile >= 64) ? 2 : 6;
+  const unsigned npers = (unsigned)std::min<int64_t>(P.nkeys, (int64_t)P.n_cu * per_cu);
   size_t lds = (size_t)a.OS2 * a.WNP * sizeof(float);
   if (MODE != kDegrid) lds += (size_t)2 * P.tile * P.tile * sizeof(double);
   switch (P.WN * 16 + P.seg_max) {

@@ -44,21 +44,14 @@ __device__ __forceinline__ float quad_xor2(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
 }
 
+// One (channel, tile) of the work: zero the accumulator, walk the tile's work
+// list, write the tile.  tabE must already hold the extended kernel table.
 template <int WN, int SMAX, int MODE, int BLOCK, int GROUP>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 4 && BLOCK < 256 ? RTS_TILE_WAVES : 2))) void k_tile(
-    TileArgs a) {
+__device__ __forceinline__ void tile_body(const TileArgs &a, const int key, const float *tabE, double *acc) {
   // GROUP lanes (2 or 4) share a segment; each owns CPL window columns.
   constexpr int kGroup = GROUP;
   constexpr int CPL = (WN + kGroup - 1) / kGroup;
   constexpr bool kFullCols = (WN % kGroup) == 0;   // every lane's columns lie in the window
-  extern __shared__ float4 smem4[];
-  float *smem = reinterpret_cast<float *>(smem4);
-  float *tabE = smem;                        // [2*OS][WNP], rows 16-byte aligned
-  // FP64 accumulator [tile][tile][2] (kGrid, kFused).  LDS float atomics are an
-  // order of magnitude slower than FP64 ones on this GPU; FP64 also keeps the
-  // tile sums nearly independent of the order the work list is visited in.
-  double *acc = reinterpret_cast<double *>(smem + a.OS2 * a.WNP);
-  const int key = xcd_remap(blockIdx.x, gridDim.x);
   const int c = key / a.nT2;
   const int rem = key - c * a.nT2;
   const int ty = rem / a.nT, tx = rem - ty * a.nT;
@@ -66,10 +59,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 
   const int x0 = tx * T, y0 = ty * T;
   const int TT = T * T;
 
-  for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += BLOCK) tabE[i] = a.tabE[i];
-  if (MODE != kDegrid)
+  if (MODE != kDegrid) {
     for (int i = threadIdx.x; i < 2 * TT; i += BLOCK) acc[i] = 0.0;
-  __syncthreads();
+    __syncthreads();
+  }
 
   const uint32_t cap = (uint32_t)a.list_cap;
   const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
@@ -326,6 +319,56 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 
       const double4 d = src[i];
       out[(((size_t)c * a.N + y0 + yy) * a.N + x0) / 2 + xx] =
           make_float4((float)d.x, (float)d.y, (float)d.z, (float)d.w);
+    }
+  }
+  __syncthreads();   // the accumulator and the reduction slots are reused by the next tile
+}
+
+#define RTS_TILE_ATTRS(BLOCK, GROUP) \
+  __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 4 && BLOCK < 256 ? RTS_TILE_WAVES : 2)))
+
+// Shared-memory layout of both launches: the extended kernel table, then the FP64
+// accumulator [tile][tile][2] (kGrid, kFused).  LDS float atomics are an order of
+// magnitude slower than FP64 ones on this GPU; FP64 also keeps the tile sums
+// nearly independent of the order the work list is visited in.
+template <int BLOCK>
+__device__ __forceinline__ float *load_table(const TileArgs &a, double *&acc) {
+  extern __shared__ float4 smem4[];
+  float *tabE = reinterpret_cast<float *>(smem4);     // [2*OS][WNP], rows 16-byte aligned
+  acc = reinterpret_cast<double *>(tabE + a.OS2 * a.WNP);
+  for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += BLOCK) tabE[i] = a.tabE[i];
+  __syncthreads();
+  return tabE;
+}
+
+// One workgroup per (channel, tile), XCD-remapped.
+template <int WN, int SMAX, int MODE, int BLOCK, int GROUP>
+__global__ RTS_TILE_ATTRS(BLOCK, GROUP) void k_tile(TileArgs a) {
+  double *acc;
+  const float *tabE = load_table<BLOCK>(a, acc);
+  tile_body<WN, SMAX, MODE, BLOCK, GROUP>(a, xcd_remap(blockIdx.x, gridDim.x), tabE, acc);
+}
+
+// Persistent launch: a few workgroups per CU pull tiles from eight queues, one
+// per XCD range of tiles, each holding its range in longest-first order (the
+// plan's LPT order); a workgroup drains the queue of its own XCD first, then
+// the others.  Every pop advances a counter, so every workgroup ends.
+template <int WN, int SMAX, int MODE, int BLOCK, int GROUP>
+__global__ RTS_TILE_ATTRS(BLOCK, GROUP) void k_tile_persistent(TileArgs a) {
+  double *acc;
+  const float *tabE = load_table<BLOCK>(a, acc);
+  __shared__ int item;
+  const int per = (a.nkeys + 7) / 8;
+  for (int k = 0; k < 8; ++k) {
+    const int qi = (blockIdx.x + k) & 7;
+    const int qlen = min(per, a.nkeys - qi * per);
+    for (;;) {
+      if (threadIdx.x == 0) item = (int)atomicAdd(&a.queue[qi], 1u);
+      __syncthreads();
+      const int it = item;
+      __syncthreads();
+      if (it >= qlen) break;
+      tile_body<WN, SMAX, MODE, BLOCK, GROUP>(a, (int)a.order[qi * per + it], tabE, acc);
     }
   }
 }

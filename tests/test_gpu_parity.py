@@ -23,9 +23,10 @@ def rts():
     return rts
 
 
-def run_all(rts, wl, freq, du, N, W, OS, tile=0, conjugate=False, seed=0):
+def run_all(rts, wl, freq, du, N, W, OS, tile=0, conjugate=False, seed=0, schedule="auto"):
     uvw, vis, w = to_dev(torch, wl)
-    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, tile=tile, conjugate=conjugate)
+    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, tile=tile, conjugate=conjugate,
+                        schedule=schedule)
     G = plan.grid(vis, w)
     rng = np.random.default_rng(seed)
     Gin_np = (0.1 * (rng.standard_normal(G.shape) + 1j * rng.standard_normal(G.shape))).astype(np.complex64)
@@ -107,6 +108,37 @@ def test_grid_degrid_fused_parity(rts, W, OS, N, tile):
                               flag_frac=0.15, offgrid_frac=0.03)
     plan, G, Gin, M, fused = run_all(rts, wl, freq, du, N, W, OS, tile=tile)
     check_against_oracle(wl, freq, du, N, W, OS, G, Gin, M, fused)
+
+
+@pytest.mark.parametrize("W,OS,N,tile,channels", [(7, 8, 256, 0, (0, 13, 31)), (7, 8, 512, 32, (0, 13, 31)),
+                                                  (12, 8, 256, 16, (3, 9)), (16, 16, 256, 64, (5,)),
+                                                  (7, 8, 64, 32, (2,))])
+def test_persistent_schedule_parity(rts, W, OS, N, tile, channels):
+    """The persistent longest-first launch gives the oracle's results, also with
+    fewer tiles than queues (N=64, tile 32: four tiles, eight queues)."""
+    wl, freq, du = small_case(n_ant=40, channels=channels, N=N, W=W, OS=OS, weights="uniform",
+                              flag_frac=0.15, offgrid_frac=0.03)
+    plan, G, Gin, M, fused = run_all(rts, wl, freq, du, N, W, OS, tile=tile, schedule="persistent")
+    check_against_oracle(wl, freq, du, N, W, OS, G, Gin, M, fused)
+
+
+def test_persistent_schedule_after_update(rts):
+    """rts_plan_update rebuilds the longest-first order with the work list."""
+    wl, freq, du = small_case(n_ant=40, channels=(0, 13, 31), N=256, weights="uniform", flag_frac=0.1)
+    wl2, _, _ = small_case(seed=5, n_ant=40, channels=(0, 13, 31), N=256, weights="uniform", flag_frac=0.1)
+    uvw, vis, w = to_dev(torch, wl)
+    uvw2, vis2, w2 = to_dev(torch, wl2)
+    plan = rts.GridPlan(uvw, freq, w, 256, du, schedule="persistent")
+    ref = rts.GridPlan(uvw2, freq, w2, 256, du, schedule="tiles")
+    for _ in range(2):
+        plan.update(uvw2, w2)
+        G = plan.grid(vis2, w2).cpu().numpy()
+        Gt = ref.grid(vis2, w2).cpu().numpy()
+        assert rel_l2(G, Gt) <= 1e-6
+    geom = O.Geometry(wl2.uvw_m, freq, wl2.weights, 256, du)
+    Gref = O.grid(geom, wl2.vis, wl2.weights)
+    for c in range(3):
+        assert rel_l2(G[c], Gref[c]) <= RTOL_L2
 
 
 @pytest.mark.parametrize("T", [1, 3, 12])
