@@ -284,6 +284,7 @@ TileArgs tile_args(const Plan &P) {
   a.B = P.B; a.T = P.T; a.ncopy = P.ncopy;
   a.OS2 = 2 * P.OS; a.WNP = P.WNP; a.WN = P.WN;
   a.vec = 0;
+  a.seg_max = P.seg_max;
   a.order = P.d_order;
   a.queue = P.d_lpt ? P.d_lpt + kLptQueue : nullptr;
   return a;

@@ -85,6 +85,7 @@ struct TileArgs {
   int OS2, WNP, WN;
   int write_model;
   int vec;                   // whole-track segments may use 16-byte vector loads and stores
+  int seg_max;               // most samples per segment (a power of two)
   const uint32_t *order;     // persistent launch: tiles in per-XCD longest-first order
   uint32_t *queue;           // persistent launch: 8 queue counters (zeroed before launch)
 };

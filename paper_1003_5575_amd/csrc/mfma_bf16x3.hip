@@ -67,15 +67,19 @@ __global__ __launch_bounds__(64 * kWaves) void k_grid_mfma_bf16x3(TileArgs a, co
   const int i16 = lane & 15, g = lane >> 4;        // MFMA operand row/column and K group
   SampleSlot *ss = slots[wave];
 
-  for (uint32_t k0 = beg; k0 < end; k0 += kChunk / 2) {
-    // Stage the chunk: two sample slots per listing (segments hold <= 2 samples here).
+  // seg_max (2, 4 or 8) sample slots per listing, kChunk / seg_max listings per chunk
+  const int lg = __builtin_ctz((unsigned)a.seg_max);
+  const uint32_t per_chunk = (uint32_t)(kChunk >> lg);
+  for (uint32_t k0 = beg; k0 < end; k0 += per_chunk) {
+    // Stage the chunk: slot lane holds sample (lane mod seg_max) of listing
+    // k0 + lane / seg_max; slots past a segment's end stay empty.
     if (lane < kChunk) {
       SampleSlot sl;
       sl.dx = sl.dy = 0;
       sl.sx = sl.sy = -1;
       sl.ar = sl.ai = 0.0f;
-      const uint32_t k = k0 + (lane >> 1);
-      const int j = lane & 1;
+      const uint32_t k = k0 + (uint32_t)(lane >> lg);
+      const int j = lane & (a.seg_max - 1);
       if (k < end) {
         const uint2 rec = a.list[k];
         const int nt = (int)((rec.y >> kRecNtShift) & 7u) + 1;
