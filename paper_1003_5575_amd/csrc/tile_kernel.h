@@ -167,84 +167,111 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     float chi2_seg = 0.0f;   // this segment's sum of w |r|^2 (SMAX terms, FP32)
     // With the 256-register budget the segment's model values are kept and
     // stored together after the sample loop; otherwise each is stored at once.
-    constexpr bool kBufModel = BLOCK >= 256;
+    constexpr bool kBufModel = BLOCK == 256;
     float2 mv[SMAX];
+    // The sample loop is straight-line code (no per-sample branches).  The
+    // kernel-table rows of sample s+1 are read from LDS before sample s is
+    // computed, and a scheduling barrier keeps the compiler from hoisting reads
+    // further ahead (which would cost registers).  A slot past the segment's end
+    // has packed coordinates 0 (not valid): it reads table row 0 and
+    // contributes nothing.
+    constexpr int KYN = (WN + 3) & ~3;
+    float kyn[KYN], kxn[CPL];
+    auto read_rows = [&](const uint32_t cw, float (&ky)[KYN], float (&kx)[CPL]) {
+      const int sx = cw & 0x7F, sy = (cw >> 7) & 0x7F;
+      const float4 *ry = reinterpret_cast<const float4 *>(tabE + sy * a.WNP);
+#pragma unroll
+      for (int j4 = 0; j4 < KYN / 4; ++j4) {
+        const float4 t4 = ry[j4];
+        ky[4 * j4] = t4.x;
+        ky[4 * j4 + 1] = t4.y;
+        ky[4 * j4 + 2] = t4.z;
+        ky[4 * j4 + 3] = t4.w;
+      }
+      const float *rx = tabE + sx * a.WNP + col0;
+      if (CPL == 2 && kFullCols) {
+        const float2 t2 = *reinterpret_cast<const float2 *>(rx);
+        kx[0] = t2.x;
+        kx[CPL - 1] = t2.y;
+      } else if (CPL == 4 && kFullCols) {
+        const float4 t4 = *reinterpret_cast<const float4 *>(rx);
+        kx[0] = t4.x;
+        kx[1 % CPL] = t4.y;
+        kx[2 % CPL] = t4.z;
+        kx[3 % CPL] = t4.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) kx[i] = (kFullCols || col0 + i < WN) ? rx[i] : 0.0f;
+      }
+    };
+    // The straight-line form with reads one sample ahead needs more registers:
+    // only with the 256-register budget.  Otherwise each sample is a branch
+    // (skipped past the segment's end) that reads its own table rows.
+    constexpr bool kAhead = BLOCK == 256;
+    if (kAhead) read_rows(cws[0], kyn, kxn);
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
-      if (s < nt) {
-        const uint32_t cw = cws[s];
-        const bool ok = (cw & kCoordValid) != 0;
-        const int sx = cw & 0x7F, sy = (cw >> 7) & 0x7F;
-        float ky[(WN + 3) & ~3], kx[CPL];
-        const float4 *ry = reinterpret_cast<const float4 *>(tabE + sy * a.WNP);
+      if (!kAhead && s >= nt) continue;
+      const uint32_t cw = cws[s];
+      const bool ok = (cw & kCoordValid) != 0;
+      float ky[KYN], kx[CPL];
+      if (kAhead) {
 #pragma unroll
-        for (int j4 = 0; j4 < (WN + 3) / 4; ++j4) {
-          const float4 t4 = ry[j4];
-          ky[4 * j4] = t4.x;
-          ky[4 * j4 + 1] = t4.y;
-          ky[4 * j4 + 2] = t4.z;
-          ky[4 * j4 + 3] = t4.w;
-        }
-        const float *rx = tabE + sx * a.WNP + col0;
-        if (CPL == 2 && kFullCols) {
-          const float2 t2 = *reinterpret_cast<const float2 *>(rx);
-          kx[0] = t2.x;
-          kx[CPL - 1] = t2.y;
-        } else if (CPL == 4 && kFullCols) {
-          const float4 t4 = *reinterpret_cast<const float4 *>(rx);
-          kx[0] = t4.x;
-          kx[1 % CPL] = t4.y;
-          kx[2 % CPL] = t4.z;
-          kx[3 % CPL] = t4.w;
-        } else {
+        for (int j = 0; j < KYN; ++j) ky[j] = kyn[j];
 #pragma unroll
-          for (int i = 0; i < CPL; ++i) kx[i] = (kFullCols || col0 + i < WN) ? rx[i] : 0.0f;
-        }
+        for (int i = 0; i < CPL; ++i) kx[i] = kxn[i];
+        if (s + 1 < SMAX) read_rows(cws[(s + 1) % SMAX], kyn, kxn);
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        read_rows(cw, ky, kx);
+      }
 
-        float2 m = make_float2(0.0f, 0.0f);
-        if (MODE != kGrid) {
+      float2 m = make_float2(0.0f, 0.0f);
+      if (MODE != kGrid) {
 #pragma unroll
-          for (int i = 0; i < CPL; ++i) {
-            float hr = 0.0f, hi = 0.0f;
+        for (int i = 0; i < CPL; ++i) {
+          float hr = 0.0f, hi = 0.0f;
 #pragma unroll
-            for (int j = 0; j < WN; ++j) {
-              hr = fmaf(ky[j], gw[j][i].x, hr);
-              hi = fmaf(ky[j], gw[j][i].y, hi);
-            }
-            m.x = fmaf(kx[i], hr, m.x);
-            m.y = fmaf(kx[i], hi, m.y);
+          for (int j = 0; j < WN; ++j) {
+            hr = fmaf(ky[j], gw[j][i].x, hr);
+            hi = fmaf(ky[j], gw[j][i].y, hi);
           }
-          m.x += quad_xor1(m.x);
-          m.y += quad_xor1(m.y);
-          if (kGroup == 4) {
-            m.x += quad_xor2(m.x);
-            m.y += quad_xor2(m.y);
-          }
-          mv[s] = ok ? m : make_float2(0.0f, 0.0f);
-          if (!kBufModel && put_model && q == 0) a.model[vi + s] = mv[s];
+          m.x = fmaf(kx[i], hr, m.x);
+          m.y = fmaf(kx[i], hi, m.y);
         }
-        if (MODE != kDegrid && ok) {
-          float2 v = vs[s];
-          const float wt = ws[s];
-          if (copy) v.y = -v.y;
-          float ar, ai;
-          if (MODE == kGrid) {
-            ar = wt * v.x;
-            ai = wt * v.y;
-          } else {
-            const float rr = v.x - m.x, ri = v.y - m.y;
-            ar = wt * rr;
-            ai = wt * ri;
-            chi2_seg = fmaf(wt, fmaf(rr, rr, ri * ri), chi2_seg);
-          }
+        m.x += quad_xor1(m.x);
+        m.y += quad_xor1(m.y);
+        if (kGroup == 4) {
+          m.x += quad_xor2(m.x);
+          m.y += quad_xor2(m.y);
+        }
+        mv[s] = ok ? m : make_float2(0.0f, 0.0f);
+        if (!kBufModel && put_model && q == 0 && s < nt) a.model[vi + s] = mv[s];
+      }
+      if (MODE != kDegrid && (kAhead || ok)) {
+        float2 v = vs[s];
+        const float wt = ws[s];
+        if (copy) v.y = -v.y;
+        float ar, ai;
+        if (MODE == kGrid) {
+          ar = wt * v.x;
+          ai = wt * v.y;
+        } else {
+          const float rr = v.x - m.x, ri = v.y - m.y;
+          ar = wt * rr;
+          ai = wt * ri;
+          const float c2 = wt * fmaf(rr, rr, ri * ri);
+          chi2_seg += ok ? c2 : 0.0f;
+        }
+        ar = ok ? ar : 0.0f;
+        ai = ok ? ai : 0.0f;
 #pragma unroll
-          for (int i = 0; i < CPL; ++i) {
-            const float br = ar * kx[i], bi = ai * kx[i];
+        for (int i = 0; i < CPL; ++i) {
+          const float br = ar * kx[i], bi = ai * kx[i];
 #pragma unroll
-            for (int j = 0; j < WN; ++j) {
-              up[j][i].x = fmaf(br, ky[j], up[j][i].x);
-              up[j][i].y = fmaf(bi, ky[j], up[j][i].y);
-            }
+          for (int j = 0; j < WN; ++j) {
+            up[j][i].x = fmaf(br, ky[j], up[j][i].x);
+            up[j][i].y = fmaf(bi, ky[j], up[j][i].y);
           }
         }
       }
@@ -325,7 +352,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
 }
 
 #define RTS_TILE_ATTRS(BLOCK, GROUP) \
-  __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(GROUP == 4 && BLOCK < 256 ? RTS_TILE_WAVES : 2)))
+  __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK != 256 ? RTS_TILE_WAVES : 2)))
 
 // Shared-memory layout of both launches: the extended kernel table, then the FP64
 // accumulator [tile][tile][2] (kGrid, kFused).  LDS float atomics are an order of
