@@ -168,7 +168,6 @@ void free_plan(Plan *P) {
   hipFree(P->d_cursor);
   hipFree(P->d_scan_tmp);
   hipFree(P->d_hist);
-  hipFree(P->d_offs);
   hipFree(P->d_desc);
   hipFree(P->d_order);
   hipFree(P->d_lpt);
@@ -241,8 +240,11 @@ PlanArgs plan_args(const Plan &P, const double *uvw, const float *w) {
   // per-track path: LDS histogram over the channels of a workgroup when it fits in 32 KiB
   a.nbx = P.nbx;
   a.chunk = P.chunk;
+  a.vec_t = (P.T == 8 || P.T == 4) && aligned(w, 16);
   a.hist = P.d_hist;
-  a.offs = P.d_offs;
+  a.offs = P.d_hist;
+  a.tile_off = P.d_tile_off;
+  a.nkeys = P.nkeys;
   a.desc = P.d_desc;
   if (P.nbx > 0) {
     a.use_lds = 0;
@@ -263,12 +265,7 @@ PlanArgs plan_args(const Plan &P, const double *uvw, const float *w) {
 // Exclusive scan of the listing counts into tile offsets (and cursors or
 // per-chunk offsets for the scatter pass).
 hipError_t scan_counts(const Plan &P, hipStream_t s) {
-  if (P.nbx > 0) {
-    const int64_t n = P.nkeys * P.nbx;
-    hipError_t e = launch_scan(P.d_hist, P.d_offs, nullptr, P.d_scan_tmp, n, s);
-    if (e != hipSuccess) return e;
-    return launch_tile_offsets(P.d_offs, P.nbx, P.nkeys, P.d_tile_off, s);
-  }
+  if (P.nbx > 0) return launch_hist_scan(P.d_hist, P.nbx, P.nkeys, P.d_cursor, P.d_tile_off, P.d_scan_tmp, s);
   return launch_scan(P.d_cursor, P.d_tile_off, P.d_cursor, P.d_scan_tmp, P.nkeys, s);
 }
 
@@ -394,8 +391,8 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
 
   const int64_t nsamp = (int64_t)P->C * P->B * P->T;
   choose_sort(*P);
-  const int64_t nscan = P->nbx > 0 ? P->nkeys * P->nbx : P->nkeys;
-  P->scan_blocks = (nscan + 4095) / 4096;
+  const int64_t nhist = P->nbx > 0 ? P->nkeys * P->nbx : 0;
+  P->scan_blocks = (P->nkeys + 4095) / 4096;
   RTS_HIP(dalloc(&P->d_tabE, P->tabE.size()));
   RTS_HIP(dalloc(&P->d_tab_hi, P->tab_hi.size()));
   RTS_HIP(dalloc(&P->d_tab_lo, P->tab_lo.size()));
@@ -407,8 +404,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   RTS_HIP(dalloc(&P->d_stats, 8));
   RTS_HIP(dalloc(&P->d_chi2_part, (size_t)P->nkeys));
   if (P->nbx > 0) {
-    RTS_HIP(dalloc(&P->d_hist, (size_t)nscan));
-    RTS_HIP(dalloc(&P->d_offs, (size_t)nscan + 1));
+    RTS_HIP(dalloc(&P->d_hist, (size_t)nhist));
     RTS_HIP(dalloc(&P->d_desc, (size_t)P->C * P->ncopy * P->B));
   }
   if (P->schedule == RTS_SCHEDULE_PERSISTENT) {
@@ -460,7 +456,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   I.seg_max = P->seg_max;
   I.workspace_bytes = (int64_t)(P->tabE.size() * 4 + P->C * 8 + nsamp * P->ncopy * 2 +
                                 (P->nkeys + 1) * 4 + P->nkeys * 4 + (P->scan_blocks + 1) * 4 + 64 +
-                                (P->nbx > 0 ? (2 * nscan + 1) * 4 + (int64_t)P->C * P->ncopy * P->B * 4 : 0) +
+                                (P->nbx > 0 ? nhist * 4 + (int64_t)P->C * P->ncopy * P->B * 4 : 0) +
                                 P->nkeys * 8 + P->list_cap * 8 +
                                 (P->d_order ? P->nkeys * 4 + kLptWords * 4 : 0));
   *out = P.release();

@@ -63,8 +63,11 @@ struct PlanArgs {
   int tgroup;             // lanes per track (power of two >= T) for the lane path, 0 = per-track path
   int nbx;                // chunked sort: track chunks (0 = not used)
   int64_t chunk;          // chunked sort: tracks per chunk
-  uint32_t *hist;         // chunked sort: [nkeys][nbx] counts
-  const uint32_t *offs;   // chunked sort: [nkeys][nbx] exclusive offsets (+1 total)
+  uint32_t *hist;         // chunked sort: [nbx][nkeys] counts (chunk-major: coalesced rows)
+  const uint32_t *offs;   // chunked sort: [nbx][nkeys] offsets of each chunk within its key
+  const uint32_t *tile_off;  // chunked sort: [nkeys + 1] first slot of each key
+  int64_t nkeys;          // C * nT2
+  int vec_t;              // T is 4 or 8 and the weights are 16-byte aligned: vector loads
   uint32_t *desc;         // chunked sort: per-track segment descriptors [C][ncopy][B]
 };
 
@@ -124,8 +127,7 @@ struct rts_plan_s {
   uint32_t *d_tile_off = nullptr;
   uint32_t *d_cursor = nullptr;
   uint32_t *d_scan_tmp = nullptr;
-  uint32_t *d_hist = nullptr;     // chunked sort counts [nkeys][nbx]
-  uint32_t *d_offs = nullptr;     // chunked sort offsets [nkeys][nbx] + 1
+  uint32_t *d_hist = nullptr;     // chunked sort counts, then in-chunk offsets [nbx][nkeys]
   uint32_t *d_desc = nullptr;     // chunked sort per-track descriptors [C][ncopy][B]
   uint32_t *d_order = nullptr;    // tiles in per-XCD longest-first order [nkeys]
   uint32_t *d_lpt = nullptr;      // LPT bucket counts, offsets, scan scratch, queues
@@ -153,8 +155,8 @@ hipError_t launch_plan_count(const PlanArgs &a, hipStream_t s);
 hipError_t launch_plan_scatter(const PlanArgs &a, hipStream_t s);
 hipError_t launch_scan(const uint32_t *counts, uint32_t *tile_off, uint32_t *cursor,
                        uint32_t *tmp, int64_t n, hipStream_t s);
-hipError_t launch_tile_offsets(const uint32_t *offs, int64_t nbx, int64_t nkeys, uint32_t *tile_off,
-                               hipStream_t s);
+hipError_t launch_hist_scan(uint32_t *hist, int nbx, int64_t nkeys, uint32_t *totals, uint32_t *tile_off,
+                            uint32_t *tmp, hipStream_t s);
 hipError_t launch_coords(const double *uvw, const double *scale, const float *w, int32_t *out,
                          int N, int W, int OS, int C, int B, int T, hipStream_t s);
 hipError_t launch_chi2_reduce(const double *part, int64_t n, double *out, hipStream_t s);

@@ -481,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
     for (int i = threadIdx.x; i < nloc; i += kBlock) bins[i] = 0u;
   } else {
     for (int i = threadIdx.x; i < nloc; i += kBlock)
-      bins[i] = a.offs[((size_t)c0 * a.nT2 + i) * a.nbx + bx];
+      bins[i] = a.offs[(size_t)bx * a.nkeys + (size_t)c0 * a.nT2 + i] + a.tile_off[(size_t)c0 * a.nT2 + i];
   }
   __syncthreads();
   const int64_t ntr = (int64_t)a.ncopy * a.B;
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
   if (!SCATTER) {
     __syncthreads();
     for (int i = threadIdx.x; i < nloc; i += kBlock)
-      a.hist[((size_t)c0 * a.nT2 + i) * a.nbx + bx] = bins[i];
+      a.hist[(size_t)bx * a.nkeys + (size_t)c0 * a.nT2 + i] = bins[i];
     const unsigned long long v0 = block_sum_u64(nvalid);
     const unsigned long long v1 = block_sum_u64(nflag);
     const unsigned long long v2 = block_sum_u64(noff);
@@ -577,7 +577,31 @@ __global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
 // walked again from memory with the same greedy rule.
 constexpr int kTrackRegs = 8;
 
-__global__ __launch_bounds__(kBlock) void k_plan_track_count(PlanArgs a) {
+typedef double rts_d2_a8 __attribute__((ext_vector_type(2), aligned(8)));
+
+// The T (<= kTrackRegs) weights of track b in channel c (vector loads when T is 4
+// or 8 and the weights are 16-byte aligned; a track then starts 16-byte aligned).
+__device__ __forceinline__ void load_track_weights(const PlanArgs &a, int c, int b, float (&w)[kTrackRegs]) {
+  const float *p = a.w + ((size_t)c * a.B + b) * a.T;
+  float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f), y = x;
+  if (a.vec_t) {
+    x = reinterpret_cast<const float4 *>(p)[0];
+    if (a.T == 8) y = reinterpret_cast<const float4 *>(p)[1];
+  } else {
+    if (a.T > 0) x.x = p[0];
+    if (a.T > 1) x.y = p[1];
+    if (a.T > 2) x.z = p[2];
+    if (a.T > 3) x.w = p[3];
+    if (a.T > 4) y.x = p[4];
+    if (a.T > 5) y.y = p[5];
+    if (a.T > 6) y.z = p[6];
+    if (a.T > 7) y.w = p[7];
+  }
+  w[0] = x.x; w[1 % kTrackRegs] = x.y; w[2 % kTrackRegs] = x.z; w[3 % kTrackRegs] = x.w;
+  w[4 % kTrackRegs] = y.x; w[5 % kTrackRegs] = y.y; w[6 % kTrackRegs] = y.z; w[7 % kTrackRegs] = y.w;
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plan_track_count(PlanArgs a) {
   extern __shared__ uint32_t bins[];                 // [cg][nT2]
   const int c0 = blockIdx.y * a.cg;
   const int c1 = min(a.C, c0 + a.cg);
@@ -597,14 +621,21 @@ __global__ __launch_bounds__(kBlock) void k_plan_track_count(PlanArgs a) {
     for (int t = 0; t < kTrackRegs; ++t) {
       u[t] = v[t] = 0.0;
       if (t < a.T) {
-        const double *p = a.uvw + ((size_t)b * a.T + t) * 3;
-        u[t] = sgn * p[0];
-        v[t] = sgn * p[1];
+        // (u, v) of one sample in one 16-byte load (8-byte aligned address)
+        const rts_d2_a8 uv = *reinterpret_cast<const rts_d2_a8 *>(a.uvw + ((size_t)b * a.T + t) * 3);
+        u[t] = sgn * uv.x;
+        v[t] = sgn * uv.y;
       }
     }
+    // The weights of the next channel are loaded while this one is processed.
+    float wn[kTrackRegs];
+    load_track_weights(a, c0, b, wn);
 #pragma unroll 1
     for (int c = c0; c < c1; ++c) {
-      const size_t base = ((size_t)c * a.B + b) * a.T;
+      float wv[kTrackRegs];
+#pragma unroll
+      for (int t = 0; t < kTrackRegs; ++t) wv[t] = wn[t];
+      if (c + 1 < c1) load_track_weights(a, c + 1, b, wn);
       const double sc = a.scale[c];
       Sample sm[kTrackRegs];
       int mnx = 1 << 30, mxx = -(1 << 30), mny = 1 << 30, mxy = -(1 << 30);
@@ -613,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_track_count(PlanArgs a) {
         sm[t].valid = sm[t].flagged = false;
         sm[t].cx = sm[t].cy = sm[t].rx = sm[t].ry = 0;
         if (t < a.T) {
-          sm[t] = sample(a, u[t], v[t], sc, a.w[base + t]);
+          sm[t] = sample(a, u[t], v[t], sc, wv[t]);
           if (copy == 0) {
             nvalid += sm[t].valid;
             nflag += sm[t].flagged;
@@ -642,17 +673,28 @@ __global__ __launch_bounds__(kBlock) void k_plan_track_count(PlanArgs a) {
         seg.any = any;
         seg.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
         seg.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+        uint32_t code[kTrackRegs];
 #pragma unroll
         for (int t = 0; t < kTrackRegs; ++t) {
-          if (t < a.T) {
-            uint16_t code = 0;
-            if (sm[t].valid) {
-              const int sx = (sm[t].cx - (seg.X0 + a.h_lo)) * a.OS + (sm[t].rx - a.r0);
-              const int sy = (sm[t].cy - (seg.Y0 + a.h_lo)) * a.OS + (sm[t].ry - a.r0);
-              code = (uint16_t)(kCoordValid | (sy << 7) | sx);
-            }
-            co[t] = code;
+          code[t] = 0u;
+          if (t < a.T && sm[t].valid) {
+            const int sx = (sm[t].cx - (seg.X0 + a.h_lo)) * a.OS + (sm[t].rx - a.r0);
+            const int sy = (sm[t].cy - (seg.Y0 + a.h_lo)) * a.OS + (sm[t].ry - a.r0);
+            code[t] = kCoordValid | (uint32_t)(sy << 7) | (uint32_t)sx;
           }
+        }
+        if (a.vec_t && a.T == 8) {
+          *reinterpret_cast<uint4 *>(co) = make_uint4(code[0] | code[1 % kTrackRegs] << 16,
+                                                      code[2 % kTrackRegs] | code[3 % kTrackRegs] << 16,
+                                                      code[4 % kTrackRegs] | code[5 % kTrackRegs] << 16,
+                                                      code[6 % kTrackRegs] | code[7 % kTrackRegs] << 16);
+        } else if (a.vec_t && a.T == 4) {
+          *reinterpret_cast<uint2 *>(co) = make_uint2(code[0] | code[1 % kTrackRegs] << 16,
+                                                      code[2 % kTrackRegs] | code[3 % kTrackRegs] << 16);
+        } else {
+#pragma unroll
+          for (int t = 0; t < kTrackRegs; ++t)
+            if (t < a.T) co[t] = (uint16_t)code[t];
         }
         a.desc[di] = ((uint32_t)any << kDescAnyBit) | ((uint32_t)seg.Y0 << kRecYShift) | (uint32_t)seg.X0;
         count(seg);
@@ -660,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_track_count(PlanArgs a) {
         a.desc[di] = kDescMulti;
         const double sg2 = sgn;
         const double *uv = a.uvw + (size_t)b * a.T * 3;
-        const float *wrow = a.w + base;
+        const float *wrow = a.w + ((size_t)c * a.B + b) * a.T;
         walk_track(a, c, b, copy, [&](const Seg &seg) {
           for (int t = seg.t0; t < seg.t0 + seg.nt; ++t) {
             const Sample s2 = sample(a, sg2 * uv[t * 3], sg2 * uv[t * 3 + 1], sc, wrow[t]);
@@ -679,7 +721,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_track_count(PlanArgs a) {
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nloc; i += kBlock)
-    a.hist[((size_t)c0 * a.nT2 + i) * a.nbx + bx] = bins[i];
+    a.hist[(size_t)bx * a.nkeys + (size_t)c0 * a.nT2 + i] = bins[i];
   const unsigned long long v0 = block_sum_u64(nvalid);
   const unsigned long long v1 = block_sum_u64(nflag);
   const unsigned long long v2 = block_sum_u64(noff);
@@ -704,7 +746,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
   const int nloc = (c1 - c0) * a.nT2;
   const int bx = blockIdx.x;
   for (int i = threadIdx.x; i < nloc; i += kBlock)
-    bins[i] = a.offs[((size_t)c0 * a.nT2 + i) * a.nbx + bx];
+    bins[i] = a.offs[(size_t)bx * a.nkeys + (size_t)c0 * a.nT2 + i] + a.tile_off[(size_t)c0 * a.nT2 + i];
   __syncthreads();
   const int64_t ntr = (int64_t)a.ncopy * a.B;
   const int64_t tr_end = min(ntr, (int64_t)bx * a.chunk + a.chunk);
@@ -760,11 +802,39 @@ __global__ __launch_bounds__(kBlock) void k_lpt_scatter(const uint32_t *tile_off
   order[pos] = (uint32_t)k;
 }
 
-// tile_off[key] = offs[key * nbx] (the first slot of the key), tile_off[nkeys] = total.
-__global__ __launch_bounds__(kBlock) void k_tile_offsets(const uint32_t *offs, int64_t nbx, int64_t nkeys,
-                                                         uint32_t *tile_off) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i <= nkeys) tile_off[i] = offs[i * nbx];
+// Chunked sort, between the passes: in place, hist[bx][k] becomes the number of
+// listings of key k in the chunks before bx, and totals[k] the count of key k.
+// A workgroup owns 32 keys; each of its 8 groups of 32 lanes sums one eighth of
+// the chunks (coalesced rows), then writes running offsets from its base.
+__global__ __launch_bounds__(kBlock) void k_hist_colscan(uint32_t *hist, int nbx, int64_t nkeys,
+                                                         uint32_t *totals) {
+  __shared__ uint32_t part[kBlock / 32][32];
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int64_t k = (int64_t)blockIdx.x * 32 + lane;
+  const int per = (nbx + kBlock / 32 - 1) / (kBlock / 32);
+  const int b0 = min(nbx, grp * per), b1 = min(nbx, b0 + per);
+  uint32_t sum = 0;
+  if (k < nkeys) {
+#pragma unroll 4
+    for (int bx = b0; bx < b1; ++bx) sum += hist[(size_t)bx * nkeys + k];
+  }
+  part[grp][lane] = sum;
+  __syncthreads();
+  uint32_t base = 0, total = 0;
+  for (int g = 0; g < kBlock / 32; ++g) {
+    const uint32_t p = part[g][lane];
+    if (g < grp) base += p;
+    total += p;
+  }
+  if (k < nkeys) {
+    for (int bx = b0; bx < b1; ++bx) {
+      const size_t i = (size_t)bx * nkeys + k;
+      const uint32_t v = hist[i];
+      hist[i] = base;
+      base += v;
+    }
+    if (grp == 0) totals[k] = total;
+  }
 }
 
 // ---------------------------------------------------------------- exclusive scan
@@ -966,11 +1036,11 @@ hipError_t launch_scan(const uint32_t *counts, uint32_t *tile_off, uint32_t *cur
   return hipGetLastError();
 }
 
-hipError_t launch_tile_offsets(const uint32_t *offs, int64_t nbx, int64_t nkeys, uint32_t *tile_off,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_offsets, dim3((unsigned)((nkeys + 1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     offs, nbx, nkeys, tile_off);
-  return hipGetLastError();
+hipError_t launch_hist_scan(uint32_t *hist, int nbx, int64_t nkeys, uint32_t *totals, uint32_t *tile_off,
+                            uint32_t *tmp, hipStream_t s) {
+  hipLaunchKernelGGL(k_hist_colscan, dim3((unsigned)((nkeys + 31) / 32)), dim3(kBlock), 0, s, hist, nbx, nkeys,
+                     totals);
+  return launch_scan(totals, tile_off, nullptr, tmp, nkeys, s);
 }
 
 hipError_t launch_lpt_order(const uint32_t *tile_off, int64_t nkeys, uint32_t *lpt, uint32_t *order,
