@@ -68,18 +68,28 @@ def touched_cells(uvw_m, freq_hz, N, du, W, OS):
     return total
 
 
+KERNEL_SOURCES = ("tile_kernel.h", "tile_dispatch.h", "tile_fused.hip", "internal.h")
+
+
+def kernel_source_sha():
+    """SHA-256 over the sources the fused tile kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1003_5575_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the fused kernel from the committed counter summary,
-    or None when the kernel source changed since the counters were taken."""
-    import hashlib
+    or None when the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_tile_fused_single_cadence_traffic.json")
-    src = os.path.join(ROOT, "paper_1003_5575_amd", "csrc", "tile_kernel.h")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_sha()
     except (OSError, ValueError):
         return None
-    if rec.get("tile_kernel_h_sha256") != sha:
+    if rec.get("kernel_sources_sha256") != sha:
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -93,7 +103,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-channels", type=int, default=16)
+    ap.add_argument("--cpu-channels", type=int, default=32,
+                    help="channels of the workload the CPU oracle runs (the whole single-cadence workload)")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "persistent"])
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 5 times (calibrates the HBM byte counters)")
@@ -138,7 +150,8 @@ def main():
     chi2 = torch.empty((), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    plan = rts.GridPlan(uvw, wl.freq_hz, w, N, wl.cell_lambda, support=W, oversample=OS, tile=args.tile)
+    plan = rts.GridPlan(uvw, wl.freq_hz, w, N, wl.cell_lambda, support=W, oversample=OS, tile=args.tile,
+                        schedule=args.schedule)
     info = plan.info
     n_valid = info["n_valid"]
     log(f"[bench] plan: {info}")
@@ -198,14 +211,17 @@ def main():
         log(f"[bench] plain: {plain}")
         del gplain, mplain
 
-    # ---- roofline of the dominant kernel (the fused tile kernel)
+    # ---- roofline of the dominant kernel (the fused tile kernel; its duration is
+    # the rts_grid_degrid call, which adds a few-microsecond chi-squared reduction)
+    block = 128 if info["tile"] <= 32 and W + 1 <= 8 else 256
+    kernel_name = f"k_tile<{W + 1}, {info['seg_max']}, 2, {block}, 4> (fused)"
     touched = touched_cells(wl.uvw_m, wl.freq_hz, N, wl.cell_lambda, W, OS)
     grid_cells = cfg.n_chan * N * N
     alg_bytes = n_valid * (8 + 4 + 8) + grid_cells * 8 + touched * 8
     achieved = alg_bytes / (fused_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "k_tile<8,8,kFused>", "kernel_ms": round(fused_ms, 4),
+                "kernel": kernel_name, "kernel_ms": round(fused_ms, 4),
                 "alg_bytes_per_launch": int(alg_bytes), "touched_cells": int(touched),
                 "full_grid_read_frac": round((n_valid * 20 + 2 * grid_cells * 8) / (fused_ms * 1e-3) / 1e9
                                              / HBM_PEAK_GBS, 4)}

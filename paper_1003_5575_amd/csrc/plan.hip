@@ -962,8 +962,16 @@ __global__ __launch_bounds__(kBlock) void k_valid_mask(const uint16_t *coords, u
 
 __global__ __launch_bounds__(1024) void k_chi2_reduce(const double *part, int64_t n, double *out) {
   __shared__ double red[16];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  // eight independent partial sums per thread keep eight loads in flight
+  double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t step = (int64_t)blockDim.x * 8;
+  int64_t i0 = threadIdx.x;
+  for (; i0 + 7 * (int64_t)blockDim.x < n; i0 += step) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) p[k] += part[i0 + k * (int64_t)blockDim.x];
+  }
+  for (int64_t i = i0; i < n; i += blockDim.x) p[0] += part[i];
+  double s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();

@@ -21,6 +21,11 @@
 
 namespace rts {
 
+// Outputs (grid tiles, model values) are written once and not read again by the
+// kernel: non-temporal stores keep them from displacing G_in windows and sample
+// data in L2.
+typedef float rts_nt_v4f __attribute__((ext_vector_type(4)));
+
 
 // Lanes per segment and window columns per lane.  A group of GROUP adjacent
 // lanes shares one segment; lane q of the group owns window columns q*CPL ..
@@ -282,7 +287,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
       if (vec) {
         float4 *m4 = reinterpret_cast<float4 *>(a.model + vi);
 #pragma unroll
-        for (int h = 0; h < SMAX / 2; ++h) m4[h] = make_float4(mv[2 * h].x, mv[2 * h].y, mv[2 * h + 1].x, mv[2 * h + 1].y);
+        for (int h = 0; h < SMAX / 2; ++h) {
+          rts_nt_v4f t4 = {mv[2 * h].x, mv[2 * h].y, mv[2 * h + 1].x, mv[2 * h + 1].y};
+          __builtin_nontemporal_store(t4, reinterpret_cast<rts_nt_v4f *>(&m4[h]));
+        }
       } else {
 #pragma unroll
         for (int s = 0; s < SMAX; ++s)
@@ -344,8 +352,8 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     for (int i = threadIdx.x; i < TT / 2; i += BLOCK) {
       const int yy = i / half, xx = i - yy * half;
       const double4 d = src[i];
-      out[(((size_t)c * a.N + y0 + yy) * a.N + x0) / 2 + xx] =
-          make_float4((float)d.x, (float)d.y, (float)d.z, (float)d.w);
+      rts_nt_v4f t4 = {(float)d.x, (float)d.y, (float)d.z, (float)d.w};
+      __builtin_nontemporal_store(t4, reinterpret_cast<rts_nt_v4f *>(&out[(((size_t)c * a.N + y0 + yy) * a.N + x0) / 2 + xx]));
     }
   }
   __syncthreads();   // the accumulator and the reduction slots are reused by the next tile
