@@ -61,11 +61,14 @@ typedef enum {
 
 typedef enum {
   RTS_PREC_FP32 = 0,    /* FP32 arithmetic, FP64 tile accumulation (all entry points) */
-  RTS_PREC_BF16X3 = 1   /* rts_grid on the matrix cores: each 16x16-cell tile is the contraction
-                           Av^T diag(wV) Au over its samples with BF16 hi+lo split operands
-                           (hi*hi + hi*lo + lo*hi, FP32 accumulation; ~16 significant bits per
-                           operand).  Tiles are 16 cells.  Degridding and the fused step of such a
-                           plan use the FP32 kernels. */
+  RTS_PREC_BF16X3 = 1   /* rts_grid and rts_degrid on the matrix cores (Eq. (1) and its adjoint
+                           per 16x16-cell tile): gridding is the contraction Av^T diag(wV) Au over
+                           the tile's samples, degridding H = Av G_tile followed by the k_x sum,
+                           with per-tile partial values added to the model with FP32 atomics.
+                           Operands are split into BF16 hi+lo (hi*hi + hi*lo + lo*hi, FP32
+                           accumulation; ~16 significant bits per operand; relative error a few
+                           1e-6).  Tiles are 16 cells.  The fused step of such a plan uses the
+                           FP32 kernels. */
 } rts_precision;
 
 typedef enum {

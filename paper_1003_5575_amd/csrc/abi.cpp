@@ -505,7 +505,10 @@ rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *
   a.gin = (const float2 *)grid;
   a.model = (float2 *)vis_out;
   a.vec = vector_ok(*plan, nullptr, nullptr, vis_out);
-  RTS_HIP(launch_tile(kDegrid, *plan, a, (hipStream_t)stream));
+  if (plan->precision == RTS_PREC_BF16X3)
+    RTS_HIP(launch_degrid_mfma(*plan, a, (hipStream_t)stream));
+  else
+    RTS_HIP(launch_tile(kDegrid, *plan, a, (hipStream_t)stream));
   return RTS_OK;
 }
 

@@ -170,6 +170,7 @@ hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s, boo
 hipError_t launch_tile(int mode, const Plan &P, const TileArgs &a, hipStream_t s);
 hipError_t prepare_tile_kernels(const Plan &P);
 hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s);
+hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s);
 hipError_t launch_lpt_order(const uint32_t *tile_off, int64_t nkeys, uint32_t *lpt, uint32_t *order, hipStream_t s);
 // Longest-first tile order for the persistent launch: tiles are bucketed by their
 // work-list length (clamped to kLptBins-1) within each eighth of the tile range.

@@ -149,12 +149,163 @@ __global__ __launch_bounds__(64 * kWaves) void k_grid_mfma_bf16x3(TileArgs a, co
   }
 }
 
+// Degridding of one 16x16 tile on the matrix cores.  For the samples of the
+// tile's work list (16 at a time, rows of the MFMA), H = Av G_tile holds, per
+// sample and tile column x, the sum over the tile's rows of k_y * G; the sample's
+// partial model value over this tile is sum_x H[s][x] k_x(x).  The window of a
+// sample that crosses tile edges is covered by its listings in each tile, so
+// the partial values are added to the (zeroed) model with FP32 atomics.  Both
+// operands of H are split hi+lo as in the gridding kernel; H is formed as one
+// K=32 contraction per term with B = [Re G; Im G] stacked along K and A holding
+// k_y in the half that selects the real or imaginary part.
+struct DegridSlot {
+  int dx, dy;     // window origin relative to the tile origin (cells)
+  int sx, sy;     // extended-table rows (-1: no sample)
+  int vi;         // model index
+};
+
+__global__ __launch_bounds__(64 * kWaves) void k_degrid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
+                                                                     const uint16_t *tab_lo) {
+  __shared__ DegridSlot dslots[kWaves][16];
+  extern __shared__ float4 smem4[];
+  float *tabE = reinterpret_cast<float *>(smem4);
+  uint16_t *thi = reinterpret_cast<uint16_t *>(tabE + a.OS2 * a.WNP);
+  uint16_t *tlo = thi + a.OS2 * a.WNP;
+  for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += 64 * kWaves) {
+    tabE[i] = a.tabE[i];
+    thi[i] = tab_hi[i];
+    tlo[i] = tab_lo[i];
+  }
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ngroups = (a.nkeys + kWaves - 1) / kWaves;
+  const int key = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave;
+  if (blockIdx.x >= (unsigned)ngroups || key >= a.nkeys) return;   // whole wave leaves together
+  const int c = key / a.nT2;
+  const int rem = key - c * a.nT2;
+  const int ty = rem / a.nT, tx = rem - ty * a.nT;
+  const int x0 = tx * kMT, y0 = ty * kMT;
+  const uint32_t cap = (uint32_t)a.list_cap;
+  const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
+  if (beg >= end) return;
+  const int i16 = lane & 15, g = lane >> 4;
+
+  // B operand, loaded once: lane (x = i16, g) holds rows 8(g & 1) + e of Re G
+  // (g < 2) or Im G (g >= 2) at tile column x.
+  bf8_t bh, bl;
+  {
+    const float2 *gt = a.gin + ((size_t)c * a.N + y0) * a.N + x0 + i16;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float2 v = gt[(size_t)(8 * (g & 1) + e) * a.N];
+      __bf16 h, l;
+      split_bf16(g < 2 ? v.x : v.y, h, l);
+      bh[e] = h;
+      bl[e] = l;
+    }
+  }
+  DegridSlot *ds = dslots[wave];
+  const int lg = __builtin_ctz((unsigned)a.seg_max);
+  const uint32_t per_chunk = (uint32_t)(16 >> lg);
+  for (uint32_t k0 = beg; k0 < end; k0 += per_chunk) {
+    // Stage 16 sample slots: slot j holds sample (j mod seg_max) of listing k0 + j / seg_max.
+    if (lane < 16) {
+      DegridSlot sl;
+      sl.dx = sl.dy = 0;
+      sl.sx = sl.sy = -1;
+      sl.vi = 0;
+      const uint32_t k = k0 + (uint32_t)(lane >> lg);
+      const int j = lane & (a.seg_max - 1);
+      if (k < end) {
+        const uint2 rec = a.list[k];
+        const int nt = (int)((rec.y >> kRecNtShift) & 7u) + 1;
+        const bool any = (rec.y >> kRecAnyBit) & 1u;
+        const int copy = (int)((rec.y >> kRecCopyBit) & 1u);
+        if (any && copy == 0 && j < nt) {
+          const size_t vi = rec.x + j;
+          const uint16_t cw = a.coords[vi + (size_t)(c * (a.ncopy - 1)) * ((size_t)a.B * a.T)];
+          if (cw & kCoordValid) {
+            sl.dx = (int)(rec.y & kRecXMask) - x0;
+            sl.dy = (int)((rec.y >> kRecYShift) & kRecXMask) - y0;
+            sl.sx = cw & 0x7F;
+            sl.sy = (cw >> 7) & 0x7F;
+            sl.vi = (int)vi;
+          }
+        }
+      }
+      ds[lane] = sl;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
+
+    // A operand: lane (s = i16, g) holds k_y of sample s at tile rows 8(g & 1) + e,
+    // in the real half (g < 2) or the imaginary half (g >= 2) of K.
+    bf8_t arh, arl, aih, ail;
+    {
+      const DegridSlot sl = ds[i16];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int ry = 8 * (g & 1) + e - sl.dy;
+        const bool in = sl.sx >= 0 && ry >= 0 && ry < a.WN;
+        const int ti = in ? sl.sy * a.WNP + ry : 0;
+        const __bf16 h = __builtin_bit_cast(__bf16, in ? thi[ti] : (uint16_t)0);
+        const __bf16 l = __builtin_bit_cast(__bf16, in ? tlo[ti] : (uint16_t)0);
+        const __bf16 z = __builtin_bit_cast(__bf16, (uint16_t)0);
+        arh[e] = g < 2 ? h : z;
+        arl[e] = g < 2 ? l : z;
+        aih[e] = g < 2 ? z : h;
+        ail[e] = g < 2 ? z : l;
+      }
+    }
+    f4_t hr = {0.0f, 0.0f, 0.0f, 0.0f}, hi = {0.0f, 0.0f, 0.0f, 0.0f};
+    hr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bh, hr, 0, 0, 0);
+    hr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bl, hr, 0, 0, 0);
+    hr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bh, hr, 0, 0, 0);
+    hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bh, hi, 0, 0, 0);
+    hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bl, hi, 0, 0, 0);
+    hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bh, hi, 0, 0, 0);
+
+    // H[s][x] sits in lane x + 16 (s / 4), register s % 4: weight by k_x and sum
+    // over the 16 columns of a row of lanes.
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const DegridSlot sl = ds[4 * g + r];
+      const int rx = i16 - sl.dx;
+      const bool in = sl.sx >= 0 && rx >= 0 && rx < a.WN;
+      const float kx = in ? tabE[sl.sx * a.WNP + rx] : 0.0f;
+      float mr = hr[r] * kx, mi = hi[r] * kx;
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        mr += __shfl_xor(mr, o, 16);
+        mi += __shfl_xor(mi, o, 16);
+      }
+      if (i16 == 0 && sl.sx >= 0) {
+        atomicAdd(&a.model[sl.vi].x, mr);
+        atomicAdd(&a.model[sl.vi].y, mi);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();   // the next chunk's slot writes follow these reads
+  }
+}
+
 }  // namespace
 
 hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   const int ngroups = (int)((P.nkeys + kWaves - 1) / kWaves);
   const size_t lds = (size_t)a.OS2 * a.WNP * (sizeof(float) + 2 * sizeof(uint16_t));
   hipLaunchKernelGGL(k_grid_mfma_bf16x3, dim3((unsigned)ngroups), dim3(64 * kWaves), lds, s, a, P.d_tab_hi,
+                     P.d_tab_lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
+  // the model is the sum of per-tile partial values: start from zero
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(a.model), (int64_t)2 * P.C * P.B * P.T, 0u, s);
+  if (e != hipSuccess) return e;
+  const int ngroups = (int)((P.nkeys + kWaves - 1) / kWaves);
+  const size_t lds = (size_t)a.OS2 * a.WNP * (sizeof(float) + 2 * sizeof(uint16_t));
+  hipLaunchKernelGGL(k_degrid_mfma_bf16x3, dim3((unsigned)ngroups), dim3(64 * kWaves), lds, s, a, P.d_tab_hi,
                      P.d_tab_lo);
   return hipGetLastError();
 }
