@@ -38,6 +38,8 @@ WORKLOAD_TEXT = {
                       "point sources, 2048x2048 complex64 grid per channel, Kaiser-Bessel W=7 OS=8",
     "batched": "batched: 512 antennas (130,816 baselines), 768 channels x 40 kHz over 139-170 MHz, 4 time "
                "steps, per-channel flags U(0,30%), 1024x1024 complex64 grid per channel, W=7 OS=8",
+    "mixed": "mixed precision: 512 antennas (130,816 baselines), 64 channels over 140-170 MHz, 8 time steps, "
+             "4096x4096 complex64 grid per channel, Kaiser-Bessel W=16 OS=16, BF16x3 matrix-core grid and degrid",
 }
 
 
@@ -130,6 +132,8 @@ def main():
     import paper_1003_5575_amd as rts
     from synth import make_workload
 
+    if args.workload == "mixed":
+        return bench_mixed(args, torch, rts, make_workload)
     dev = torch.device("cuda:0")
     t0 = time.time()
     wl = make_workload(args.workload, seed=args.seed)
@@ -280,6 +284,97 @@ def main():
         "parity": parity,
         "context": {"paper_gpu_gridding_mvis_s_derived": 2.66, "paper_hardware": "Tesla C1060",
                     "realtime_budget": "5 GiB/s input, 8 s cadence, ~2.5 TFLOP/s whole pipeline"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_mixed(args, torch, rts, make_workload):
+    """The mixed-precision configuration: a step is the plan update plus BF16x3
+    gridding and BF16x3 degridding (two launches over all channels).  The FP32
+    path on the same inputs is timed beside it, and the BF16x3 error against the
+    FP64 oracle is reported per channel on a sample of channels."""
+    dev = torch.device("cuda:0")
+    wl = make_workload("mixed", seed=args.seed)
+    cfg = wl.cfg
+    N, W, OS = cfg.n_grid, cfg.support, cfg.oversample
+    uvw = torch.from_numpy(wl.uvw_m).to(dev)
+    vis = torch.from_numpy(wl.vis).to(dev)
+    w = torch.from_numpy(wl.weights).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed + 7)
+    shape = (cfg.n_chan, N, N)
+    gin = torch.complex(torch.randn(shape, generator=gen, device=dev) * 0.1,
+                        torch.randn(shape, generator=gen, device=dev) * 0.1)
+    gout = torch.empty(shape, dtype=torch.complex64, device=dev)
+    model = torch.empty_like(vis)
+    stream = torch.cuda.current_stream()
+    plan = rts.GridPlan(uvw, wl.freq_hz, w, N, wl.cell_lambda, support=W, oversample=OS, precision="bf16x3")
+    info = plan.info
+    n_valid = info["n_valid"]
+    log(f"[bench] mixed plan: {info}")
+
+    def timed(p, K):
+        for _ in range(args.warmup):
+            p.update(uvw, w); p.grid(vis, w, out=gout); p.degrid(gin, out=model)
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+        t0 = time.perf_counter()
+        for k in range(K):
+            ev[k][0].record(stream)
+            p.update(uvw, w)
+            ev[k][1].record(stream)
+            p.grid(vis, w, out=gout)
+            ev[k][2].record(stream)
+            p.degrid(gin, out=model)
+            ev[k][3].record(stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / K * 1e3
+        parts = [float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)])) for i in range(3)]
+        return ms, parts
+
+    K = args.steps
+    ms, (plan_ms, g_ms, d_ms) = timed(plan, K)
+    # per-channel error of this build's BF16x3 results on sampled channels
+    errs = None
+    if not args.no_cpu:
+        from oracle import cpu as ocpu
+        chans = np.linspace(0, cfg.n_chan - 1, 4).round().astype(int)
+        Gb = gout[chans].cpu().numpy()
+        Mb = model[chans].cpu().numpy()
+        tc = time.perf_counter()
+        Go = ocpu.grid(wl.uvw_m, wl.freq_hz[chans], wl.vis[chans], wl.weights[chans], N, wl.cell_lambda, W, OS)
+        Mo = ocpu.degrid(wl.uvw_m, wl.freq_hz[chans], wl.weights[chans], gin[chans].cpu().numpy(), N,
+                         wl.cell_lambda, W, OS)
+        t_cpu = time.perf_counter() - tc
+        errs = {"channels": [int(c) for c in chans],
+                "grid_rel_l2": [float(np.linalg.norm(Gb[i] - Go[i]) / np.linalg.norm(Go[i])) for i in range(len(chans))],
+                "degrid_rel_l2": [float(np.linalg.norm(Mb[i] - Mo[i]) / np.linalg.norm(Mo[i])) for i in range(len(chans))],
+                "oracle_seconds": round(t_cpu, 2), "oracle_cores": int(ocpu.num_threads())}
+        log(f"[bench] mixed errors: {errs}")
+    plan.close()
+    plan32 = rts.GridPlan(uvw, wl.freq_hz, w, N, wl.cell_lambda, support=W, oversample=OS)
+    ms32, (p32, g32, d32) = timed(plan32, K)
+    tile32 = plan32.info["tile"]
+    plan32.close()
+    # dense matrix-core work of the BF16x3 kernels: 3 products of 16x16x32 per
+    # 32 (grid) / 16 (degrid) sample slots per real/imaginary part of a tile
+    nl = info["n_listings"]
+    slots = nl * info["seg_max"]
+    mfma_flops = (slots / 32 * 6 + slots / 16 * 6) * 2 * 16 * 16 * 32
+    out = {
+        "metric": METRIC, "value": round(n_valid / ms / 1e3, 1), "unit": "Mvis/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["mixed"], "n_valid": int(n_valid), "n_chan": cfg.n_chan,
+                   "n_grid": N, "support": W, "oversample": OS, "tile": info["tile"],
+                   "step": "plan update + BF16x3 grid + BF16x3 degrid, one launch each over all channels"},
+        "breakdown": {"plan_ms": round(plan_ms, 4), "grid_ms": round(g_ms, 4), "degrid_ms": round(d_ms, 4),
+                      "n_listings": nl, "seg_max": info["seg_max"],
+                      "mfma_dense_tflops": round(mfma_flops / ((g_ms + d_ms) * 1e-3) / 1e12, 1),
+                      "mfma_bf16_peak_tflops": 2500.0},
+        "fp32_path": {"ms_per_step": round(ms32, 4), "value": round(n_valid / ms32 / 1e3, 1), "tile": tile32,
+                      "plan_ms": round(p32, 4), "grid_ms": round(g32, 4), "degrid_ms": round(d32, 4)},
+        "bf16x3_error": errs,
     }
     print(json.dumps(out), flush=True)
 
