@@ -31,16 +31,13 @@ namespace rts {
 #ifndef RTS_TILE64_BLOCK
 #define RTS_TILE64_BLOCK 256
 #endif
-#ifndef RTS_SMALL_W_GROUP
-#define RTS_SMALL_W_GROUP 4
-#endif
 // Small tiles with windows up to 8 cells use 128-thread workgroups (128
 // registers, four waves per SIMD); everything else 256-thread workgroups with
 // the 256-register budget (wider windows would spill with 128).
 #define RTS_TILE_CASE(WNV, SM)                                                        \
   case (WNV)*16 + (SM):                                                               \
-    if (P.tile <= 32 && (WNV) <= 8) RTS_TILE_LAUNCH(WNV, SM, ((WNV) <= 8 ? 128 : 256), RTS_SMALL_W_GROUP) \
-    else RTS_TILE_LAUNCH(WNV, SM, RTS_TILE64_BLOCK, ((WNV) <= 9 ? RTS_SMALL_W_GROUP : 4))  \
+    if (P.tile <= 32 && (WNV) <= 8) RTS_TILE_LAUNCH(WNV, SM, ((WNV) <= 8 ? 128 : 256), 4) \
+    else RTS_TILE_LAUNCH(WNV, SM, RTS_TILE64_BLOCK, 4)                                    \
     break;
 
 template <int MODE>

@@ -53,7 +53,8 @@ __device__ __forceinline__ float quad_xor2(float v) {
 // list, write the tile.  tabE must already hold the extended kernel table.
 template <int WN, int SMAX, int MODE, int BLOCK, int GROUP>
 __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, const float *tabE, double *acc) {
-  // GROUP lanes (2 or 4) share a segment; each owns CPL window columns.
+  // GROUP (= 4) lanes share a segment; each owns CPL window columns.
+  static_assert(GROUP == 4, "the DPP reductions and the quad layout assume four lanes per segment");
   constexpr int kGroup = GROUP;
   constexpr int CPL = (WN + kGroup - 1) / kGroup;
   constexpr bool kFullCols = (WN % kGroup) == 0;   // every lane's columns lie in the window
@@ -246,10 +247,8 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         }
         m.x += quad_xor1(m.x);
         m.y += quad_xor1(m.y);
-        if (kGroup == 4) {
-          m.x += quad_xor2(m.x);
-          m.y += quad_xor2(m.y);
-        }
+        m.x += quad_xor2(m.x);
+        m.y += quad_xor2(m.y);
         mv[s] = ok ? m : make_float2(0.0f, 0.0f);
         if (!kBufModel && put_model && q == 0 && s < nt) a.model[vi + s] = mv[s];
       }
