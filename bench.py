@@ -109,6 +109,7 @@ def main():
                     help="channels of the workload the CPU oracle runs (the whole single-cadence workload)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "persistent"])
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-image", action="store_true", help="skip timing the imager (rts_image)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 5 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -215,6 +216,29 @@ def main():
         log(f"[bench] plain: {plain}")
         del gplain, mplain
 
+    # ---- imager (the step after gridding; not part of the timed step): grid ->
+    # dirty image for every channel, one rts_image call
+    imager = None
+    if not args.no_image:
+        img = torch.empty_like(gout)
+        plan.image(gout, out=img)          # first call builds the FFT plan
+        torch.cuda.synchronize()
+        evi = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        evi[0].record(stream)
+        for _ in range(5):
+            plan.image(gout, out=img)
+        evi[1].record(stream)
+        torch.cuda.synchronize()
+        im_ms = evi[0].elapsed_time(evi[1]) / 5
+        pix = cfg.n_chan * N * N
+        im_bytes = 2 * pix * 8          # grid read once, image written once
+        imager = {"ms": round(im_ms, 4), "mpix_per_s": round(pix / im_ms / 1e3, 1),
+                  "alg_bytes": im_bytes, "achieved_gbs": round(im_bytes / (im_ms * 1e-3) / 1e9, 1),
+                  "frac_of_hbm_peak": round(im_bytes / (im_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "fft": "hipFFT batched in-place C2C inverse; sign and grid-correction passes are library kernels"}
+        log(f"[bench] imager: {imager}")
+        del img
+
     # ---- roofline of the dominant kernel (the fused tile kernel; its duration is
     # the rts_grid_degrid call, which adds a few-microsecond chi-squared reduction)
     block = 128 if info["tile"] <= 32 and W + 1 <= 8 else 256
@@ -279,6 +303,7 @@ def main():
                       "fused_kernel_value": round(n_valid / fused_ms / 1e3, 1),
                       "n_segments": info["n_segments"], "n_listings": info["n_listings"]},
         "plain_path": plain,
+        "imager": imager,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -187,6 +187,18 @@ rts_status rts_compute_coords(const rts_params *params, const double *uvw_m,
  * gradients of the chi-squared step, whose residual is zero at invalid samples. */
 rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream);
 
+/* Dirty image of every channel's grid (the imaging step after gridding,
+ * Section 4): image[c] = shift(IFFT2(shift(grid[c]))) / (khat(nu_y) khat(nu_x)),
+ * the centred inverse 2-D FFT without 1/N^2 normalisation, divided by the
+ * separable grid correction, khat the Fourier transform of the plan's
+ * Kaiser-Bessel window and nu = (q - N/2) / N for pixel q (pixel N/2 is l = 0).
+ * grid and image_out: complex64 [C][N][N] device buffers, 16-byte aligned,
+ * caller-owned; they may be the same buffer (in place).  The first call builds
+ * the plan's FFT plan (batched over channels) and correction table, which
+ * allocates device memory; later calls allocate nothing.  Asynchronous on
+ * `stream`.  Errors: RTS_E_INVALID (NULL or misaligned), RTS_E_NOMEM, RTS_E_HIP. */
+rts_status rts_image(rts_plan_t plan, const float *grid, float *image_out, void *stream);
+
 /* Copy the FP32 kernel table tab[p][j] = k(t_j - r_p/OS) (OS rows, W columns; rows
  * are phases r0..r0+OS-1, columns taps t0..t0+W-1 with r0 = -(OS/2), t0 = -(W-1)/2
  * for odd W and r0 = 0, t0 = -W/2+1 for even W) into host memory `tab`

@@ -166,6 +166,17 @@ class GridPlan:
         _lib.check(_lib.load().rts_degrid(self.handle, _ptr(grid), _ptr(out), _stream(stream)), "rts_degrid")
         return out
 
+    def image(self, grid, out=None, stream=None):
+        """Dirty image of every channel: complex64 [C][N][N], the centred inverse FFT of
+        the grid (unnormalised) divided by the grid correction (rts_image)."""
+        torch = _torch()
+        _check_dev(grid, "grid", torch.complex64, self._grid_shape())
+        if out is None:
+            out = torch.empty(self._grid_shape(), dtype=torch.complex64, device=grid.device)
+        _check_dev(out, "out", torch.complex64, self._grid_shape())
+        _lib.check(_lib.load().rts_image(self.handle, _ptr(grid), _ptr(out), _stream(stream)), "rts_image")
+        return out
+
     def grid_degrid(self, vis, weights, grid_in, model_out=True, grid_out=None, chi2_out=True,
                     stream=None):
         """Fused residual step.  Returns (model or None, grid_out, chi2 tensor or None)."""

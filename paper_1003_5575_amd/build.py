@@ -14,7 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librtsgrid.so")
-SOURCES = ["abi.cpp", "runtime.cpp", "plan.hip", "tile_grid.hip", "tile_degrid.hip", "tile_fused.hip", "mfma_bf16x3.hip"]
+SOURCES = ["abi.cpp", "runtime.cpp", "plan.hip", "tile_grid.hip", "tile_degrid.hip", "tile_fused.hip", "mfma_bf16x3.hip",
+           "imager.hip"]
 ARCH = os.environ.get("RTSGRID_ARCH", "gfx950")
 
 
@@ -54,7 +55,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lhipfft"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -22,6 +22,19 @@ void set_error(const char *fmt, ...) {
   g_error = buf;
 }
 
+// Modified Bessel function of the first kind, order 0, from its power series
+// sum_k ((x/2)^2)^k / (k!)^2 (all terms positive, so no cancellation).
+double bessel_i0(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 500; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
 namespace {
 
 #define RTS_HIP(expr)                                                                   \
@@ -41,18 +54,6 @@ namespace {
     }                            \
   } while (0)
 
-// Modified Bessel function of the first kind, order 0, from its power series
-// sum_k ((x/2)^2)^k / (k!)^2 (all terms positive, so no cancellation).
-double bessel_i0(double x) {
-  const double q = 0.25 * x * x;
-  double term = 1.0, sum = 1.0;
-  for (int k = 1; k < 500; ++k) {
-    term *= q / ((double)k * (double)k);
-    sum += term;
-    if (term < 1e-17 * sum) break;
-  }
-  return sum;
-}
 
 // Kaiser-Bessel window of support W, zero at and beyond |t| = W/2.
 double kaiser_bessel(double t, int W, double beta) {
@@ -158,6 +159,7 @@ void fill_tables(Plan &P) {
 
 void free_plan(Plan *P) {
   if (!P) return;
+  destroy_imager(P);
   hipFree(P->d_tabE);
   hipFree(P->d_tab_hi);
   hipFree(P->d_tab_lo);

@@ -114,6 +114,8 @@ struct rts_plan_s {
   int64_t nkeys = 0;
   int device = 0;
   int n_cu = 256;                  // compute units of the plan's device
+  void *fft = nullptr;             // imager: batched 2-D inverse FFT plan (created on first use)
+  float *d_rcorr = nullptr;        // imager: 1 / khat((i - N/2) / N), i < N
   std::vector<float> tab;    // [OS][W]
   std::vector<float> tabE;   // [2*OS][WNP]
   std::vector<uint16_t> tab_hi, tab_lo;   // [2*OS][WNP] bf16 bits: hi = bf16(k), lo = bf16(k - hi)
@@ -170,6 +172,8 @@ hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s, boo
 hipError_t launch_tile(int mode, const Plan &P, const TileArgs &a, hipStream_t s);
 hipError_t prepare_tile_kernels(const Plan &P);
 hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s);
+double bessel_i0(double x);
+void destroy_imager(Plan *P);
 hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s);
 hipError_t launch_lpt_order(const uint32_t *tile_off, int64_t nkeys, uint32_t *lpt, uint32_t *order, hipStream_t s);
 // Longest-first tile order for the persistent launch: tiles are bucketed by their

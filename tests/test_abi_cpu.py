@@ -94,6 +94,7 @@ def test_calls_on_null_plan(lib):
     assert lib.rts_plan_update(None, None, None, None) == 1
     assert lib.rts_plan_get_info(None, None) == 1
     assert lib.rts_plan_get_table(None, None, 0) == 1
+    assert lib.rts_image(None, None, None, None) == 1
     assert "plan is NULL" in lib.rts_last_error().decode()
 
 

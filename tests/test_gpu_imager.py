@@ -1,0 +1,92 @@
+"""Imager (grid -> dirty image, the step after gridding) against the FP64 oracle.
+
+The oracle's image is pinned in tests/test_oracle_pins.py against a brute-force
+direct DFT; here the GPU image (hipFFT batched inverse transform between the
+library's sign and grid-correction passes) must match it per channel within the
+FP32 bound (1e-5, or four times the error of a plain complex64 CPU FFT of the
+same grid where the single-precision transform itself rounds more), for odd and
+even supports, in place and out of place."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests.gpu_helpers import RTOL_L2, rel_l2, small_case, to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rts():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1003_5575_amd as rts
+    rts._lib.load()
+    return rts
+
+
+@pytest.mark.parametrize("W,OS,N,conj", [(7, 8, 256, True), (8, 8, 128, False), (16, 16, 256, True)])
+def test_image_matches_oracle(rts, W, OS, N, conj):
+    wl, freq, du = small_case(n_ant=40, channels=(0, 13, 31), N=N, W=W, OS=OS, weights="uniform", flag_frac=0.1)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, conjugate=conj)
+    G = plan.grid(vis, w)
+    img = plan.image(G).cpu().numpy()
+    G64 = G.cpu().numpy().astype(np.complex128)
+    ref = O.image(G64, W, O.default_beta(W))
+    # The FP32 2-D FFT itself rounds at each of its log2(N^2) stages; its error
+    # is measured with a plain complex64 CPU pipeline of the same operation
+    # (numpy's FFT in single precision), and the GPU must be within 4x of it.
+    nu = (np.arange(N) - N // 2) / N
+    corr = O.kb_hat(nu, W, O.default_beta(W)).astype(np.float32)
+    G32 = G.cpu().numpy()
+    ref32 = (np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(G32, axes=(-2, -1)).astype(np.complex64)).astype(np.complex64),
+                             axes=(-2, -1)) * np.float32(N * N)) / (corr[:, None] * corr[None, :])
+    for c in range(len(freq)):
+        e32 = rel_l2(ref32[c], ref[c])
+        err = rel_l2(img[c], ref[c])
+        print(f"imager W={W} N={N} channel {c}: rel L2 {err:.2e} (complex64 CPU FFT: {e32:.2e})")
+        assert err <= max(RTOL_L2, 4 * e32), f"channel {c}"
+    if conj:
+        # Hermitian grid -> real image.  Checked on the central half of the field:
+        # towards the edges the grid correction divides by khat values down to
+        # 1e-4 of khat(0) (W=16), which lifts single-precision rounding there.
+        q = slice(N // 4, 3 * N // 4)
+        inner = img[:, q, q]
+        assert np.linalg.norm(inner.imag) <= 1e-5 * np.linalg.norm(inner.real)
+
+
+def test_image_in_place_and_repeat(rts):
+    wl, freq, du = small_case(n_ant=32, channels=(4, 20), N=128, W=7, OS=8)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, 128, du)
+    G = plan.grid(vis, w)
+    a = plan.image(G).cpu().numpy()
+    b = plan.image(G).cpu().numpy()
+    assert np.array_equal(a, b)
+    H = G.clone()
+    plan.image(H, out=H)
+    assert rel_l2(H.cpu().numpy(), a) <= 1e-7
+
+
+def test_point_source_image_peaks_at_its_pixel(rts):
+    """One visibility of a unit point source at pixel (qy, qx) on every baseline:
+    the image peaks at that pixel."""
+    from synth import make_workload
+    N, W = 256, 7
+    wl = make_workload("tiny", seed=3)
+    freq = wl.freq_hz[wl.channels]
+    du = wl.cell_lambda
+    qy, qx = N // 2 + 9, N // 2 - 14
+    l, m = (qx - N // 2) / (N * du), (qy - N // 2) / (N * du)
+    lam = O.C_LIGHT / freq[0]
+    u = wl.uvw_m[:, :, 0] / lam
+    v = wl.uvw_m[:, :, 1] / lam
+    vis = np.exp(-2j * np.pi * (u * l + v * m))[None].astype(np.complex64)
+    weights = np.ones_like(vis.real, dtype=np.float32)
+    dev = torch.device("cuda:0")
+    uvw_d = torch.from_numpy(np.ascontiguousarray(wl.uvw_m)).to(dev)
+    plan = rts.GridPlan(uvw_d, freq, torch.from_numpy(weights).to(dev), N, du, support=W, oversample=8, conjugate=True)
+    G = plan.grid(torch.from_numpy(vis).to(dev), torch.from_numpy(weights).to(dev))
+    img = plan.image(G).cpu().numpy()[0].real
+    assert np.unravel_index(np.argmax(img), img.shape) == (qy, qx)
