@@ -38,6 +38,10 @@ WORKLOAD_TEXT = {
                       "point sources, 2048x2048 complex64 grid per channel, Kaiser-Bessel W=7 OS=8",
     "batched": "batched: 512 antennas (130,816 baselines), 768 channels x 40 kHz over 139-170 MHz, 4 time "
                "steps, per-channel flags U(0,30%), 1024x1024 complex64 grid per channel, W=7 OS=8",
+    "tiny": "plain gridding, tiny: 32 antennas (496 baselines), 1 time step, 1 channel at 150 MHz, 256x256 "
+            "complex64 grid, Kaiser-Bessel W=7 OS=8 (launch latency)",
+    "differentiated": "differentiated: as single_cadence with weights U(0.5,1.5); chi-squared "
+                      "sum w|V - degrid(G)|^2 and its gradients with respect to G and w (torch.autograd)",
     "mixed": "mixed precision: 512 antennas (130,816 baselines), 64 channels over 140-170 MHz, 8 time steps, "
              "4096x4096 complex64 grid per channel, Kaiser-Bessel W=16 OS=16, BF16x3 matrix-core grid and degrid",
 }
@@ -216,6 +220,52 @@ def main():
         log(f"[bench] plain: {plain}")
         del gplain, mplain
 
+    # ---- the same step replayed from a captured HIP graph (rts_cadence_graph_*)
+    graph = None
+    try:
+        g = plan.cadence_graph(uvw, vis, w, gin, model, gout, chi2)
+        for _ in range(2):
+            g.launch()
+        torch.cuda.synchronize()
+        evg = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        tg = time.perf_counter()
+        evg[0].record(stream)
+        for _ in range(K):
+            g.launch()
+        evg[1].record(stream)
+        torch.cuda.synchronize()
+        g_ms = (time.perf_counter() - tg) / K * 1e3
+        graph = {"ms_per_step": round(g_ms, 4), "gpu_ms_per_step": round(evg[0].elapsed_time(evg[1]) / K, 4),
+                 "value": round(n_valid / g_ms / 1e3, 1)}
+        g.close()
+        log(f"[bench] graph: {graph}")
+    except Exception as e:      # e.g. conjugate plans, which the fused step rejects
+        log(f"[bench] graph: skipped ({e})")
+
+    # ---- differentiated configuration: forward (fused pass) + backward of the
+    # chi-squared with respect to the grid and the weights, through torch.autograd
+    autograd = None
+    if args.workload == "differentiated":
+        from paper_1003_5575_amd import autograd as ag
+        Gp = gin.clone().requires_grad_(True)
+        wp = w.clone().requires_grad_(True)
+        def fb():
+            Gp.grad = None; wp.grad = None
+            loss = ag.chi2(vis, wp, Gp, plan)
+            loss.backward()
+        for _ in range(2):
+            plan.update(uvw, w); fb()
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        for _ in range(K):
+            plan.update(uvw, w); fb()
+        torch.cuda.synchronize()
+        a_ms = (time.perf_counter() - tf) / K * 1e3
+        autograd = {"ms_per_step": round(a_ms, 4), "value": round(n_valid / a_ms / 1e3, 1),
+                    "step": "plan update + chi2 forward (one fused pass) + backward (dL/dG, dL/dw)"}
+        log(f"[bench] autograd: {autograd}")
+        del Gp, wp
+
     # ---- imager (the step after gridding; not part of the timed step): grid ->
     # dirty image for every channel, one rts_image call
     imager = None
@@ -303,6 +353,8 @@ def main():
                       "fused_kernel_value": round(n_valid / fused_ms / 1e3, 1),
                       "n_segments": info["n_segments"], "n_listings": info["n_listings"]},
         "plain_path": plain,
+        "graph": graph,
+        "autograd": autograd,
         "imager": imager,
         "roofline": roofline,
         "cpu_baseline": cpu,
