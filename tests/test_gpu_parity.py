@@ -166,6 +166,18 @@ def test_conjugate_grid_parity_and_hermitian(rts):
         assert rel_l2(mirror, np.conj(G[c])) <= 1e-6
 
 
+@pytest.mark.parametrize("W,OS,N,tile", [(8, 8, 256, 0), (16, 16, 256, 0), (12, 8, 256, 16)])
+def test_conjugate_grid_even_and_wide_supports(rts, W, OS, N, tile):
+    """Conjugate gridding with even and wide supports (64-cell and 16-cell tiles):
+    oracle parity and Hermitian symmetry about the grid centre."""
+    wl, freq, du = small_case(n_ant=40, channels=(0, 31), N=N, W=W, OS=OS, weights="uniform", flag_frac=0.1)
+    plan, G, Gin, M, fused = run_all(rts, wl, freq, du, N, W, OS, tile=tile, conjugate=True)
+    check_against_oracle(wl, freq, du, N, W, OS, G, Gin, M, fused, conjugate=True)
+    idx = (N - np.arange(N)) % N
+    for c in range(2):
+        assert rel_l2(G[c][idx][:, idx], np.conj(G[c])) <= 1e-6
+
+
 def test_everything_flagged_gives_zeros(rts):
     wl, freq, du = small_case(n_ant=20, channels=(0, 5), N=128)
     wl.weights[:] = 0
