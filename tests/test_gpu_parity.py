@@ -266,3 +266,14 @@ def test_fast_moving_tracks_split_into_segments(rts, cadence_s, T):
     info = plan.info
     assert info["n_segments"] > 2 * wl.vis.shape[0] * wl.vis.shape[1]   # most tracks split
     check_against_oracle(wl, freq, du, 256, 7, 8, G, Gin, M, fused)
+
+
+def test_maximum_sizes(rts):
+    """The largest grid, support and oversampling the library accepts (N = 8192,
+    W = 16, OS = 64) on one channel: grid, degrid and the fused step against the
+    oracle."""
+    N, W, OS = 8192, 16, 64
+    wl, freq, du = small_case(n_ant=40, channels=(17,), N=N, W=W, OS=OS, weights="uniform", flag_frac=0.1)
+    plan, G, Gin, M, fused = run_all(rts, wl, freq, du, N, W, OS)
+    assert plan.info["tile"] == 64
+    check_against_oracle(wl, freq, du, N, W, OS, G, Gin, M, fused)
