@@ -118,8 +118,8 @@ def main():
                     help="only copy a 1 GiB buffer 5 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; the channel-sharded multi-GPU "
-                                   "layout is a design note, not a launch path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "one GPU only: channels would shard across GPUs with no exchange, "
+                                   "but that layout is not a launch path of this library", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -411,7 +411,7 @@ def bench_mixed(args, torch, rts, make_workload):
 
     K = args.steps
     ms, (plan_ms, g_ms, d_ms) = timed(plan, K)
-    # per-channel error of this build's BF16x3 results on sampled channels
+    # per-channel error of the BF16x3 results on sampled channels
     errs = None
     if not args.no_cpu:
         from oracle import cpu as ocpu

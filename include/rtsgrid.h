@@ -36,8 +36,11 @@
  * propagate; NaN or Inf in uvw make the sample invalid.
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  All calls
- * enqueue asynchronously on it; only rts_grid_plan synchronises it (once, to
- * size the work list).  One plan must not be used concurrently on two streams.
+ * enqueue asynchronously on it, except: rts_grid_plan synchronises it (once, to
+ * size the work list); rts_plan_get_info waits for the last re-plan's counts;
+ * the first rts_image call of a plan builds its FFT plan and correction table
+ * (allocation and a synchronous copy); rts_autotune_tile times on the stream.
+ * One plan must not be used concurrently on two streams.
  */
 #ifndef RTSGRID_H
 #define RTSGRID_H
@@ -195,8 +198,9 @@ rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream);
  * grid and image_out: complex64 [C][N][N] device buffers, 16-byte aligned,
  * caller-owned; they may be the same buffer (in place).  The first call builds
  * the plan's FFT plan (batched over channels) and correction table, which
- * allocates device memory; later calls allocate nothing.  Asynchronous on
- * `stream`.  Errors: RTS_E_INVALID (NULL or misaligned), RTS_E_NOMEM, RTS_E_HIP. */
+ * allocates device memory and copies the table synchronously; later calls
+ * allocate nothing and are asynchronous on `stream`.
+ * Errors: RTS_E_INVALID (NULL or misaligned), RTS_E_NOMEM, RTS_E_HIP. */
 rts_status rts_image(rts_plan_t plan, const float *grid, float *image_out, void *stream);
 
 /* Copy the FP32 kernel table tab[p][j] = k(t_j - r_p/OS) (OS rows, W columns; rows

@@ -3,7 +3,7 @@
 // Section 5.2 of the paper gives each block of pixels to one thread block and lets
 // it read only the visibilities binned near it, staging them in shared memory.
 // Here a workgroup owns a tile x tile square of one channel's grid in LDS
-// (complex FP32 accumulator, no global atomics on grid data) and walks the work
+// (FP64 accumulator, no global atomics on grid data) and walks the work
 // list of segments whose (W+1)x(W+1) window touches the tile.  A quad of lanes
 // handles one segment: up to SMAX consecutive samples of one baseline that share
 // the window, so the G_in window and the accumulated update stay in registers
