@@ -433,11 +433,7 @@ def bench_mixed(args, torch, rts, make_workload):
     ms32, (p32, g32, d32) = timed(plan32, K)
     tile32 = plan32.info["tile"]
     plan32.close()
-    # dense matrix-core work of the BF16x3 kernels: 3 products of 16x16x32 per
-    # 32 (grid) / 16 (degrid) sample slots per real/imaginary part of a tile
     nl = info["n_listings"]
-    slots = nl * info["seg_max"]
-    mfma_flops = (slots / 32 * 6 + slots / 16 * 6) * 2 * 16 * 16 * 32
     out = {
         "metric": METRIC, "value": round(n_valid / ms / 1e3, 1), "unit": "Mvis/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
@@ -446,9 +442,7 @@ def bench_mixed(args, torch, rts, make_workload):
                    "n_grid": N, "support": W, "oversample": OS, "tile": info["tile"],
                    "step": "plan update + BF16x3 grid + BF16x3 degrid, one launch each over all channels"},
         "breakdown": {"plan_ms": round(plan_ms, 4), "grid_ms": round(g_ms, 4), "degrid_ms": round(d_ms, 4),
-                      "n_listings": nl, "seg_max": info["seg_max"],
-                      "mfma_dense_tflops": round(mfma_flops / ((g_ms + d_ms) * 1e-3) / 1e12, 1),
-                      "mfma_bf16_peak_tflops": 2500.0},
+                      "n_listings": nl, "seg_max": info["seg_max"]},
         "fp32_path": {"ms_per_step": round(ms32, 4), "value": round(n_valid / ms32 / 1e3, 1), "tile": tile32,
                       "plan_ms": round(p32, 4), "grid_ms": round(g32, 4), "degrid_ms": round(d32, 4)},
         "bf16x3_error": errs,

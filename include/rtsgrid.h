@@ -70,8 +70,9 @@ typedef enum {
                            with per-tile partial values added to the model with FP32 atomics.
                            Operands are split into BF16 hi+lo (hi*hi + hi*lo + lo*hi, FP32
                            accumulation; ~16 significant bits per operand; relative error a few
-                           1e-6).  Tiles are 16 cells.  The fused step of such a plan uses the
-                           FP32 kernels. */
+                           1e-6).  The plan's tile (a multiple of 16 cells) is split into 16x16
+                           subtiles, one wave each.  The fused step of such a plan uses the FP32
+                           kernels. */
 } rts_precision;
 
 typedef enum {
@@ -93,7 +94,7 @@ typedef struct {
   double beta;          /* Kaiser-Bessel shape; <= 0 selects 2.34 * W                     */
   int32_t conjugate;    /* 1: also grid conj(w V) at (-u, -v) (rts_grid only)             */
   int32_t tile;         /* uv tile edge in cells: even, divides N, >= W+1, <= 64; 0 = choose
-                           (BF16x3 plans: 0 or 16)                                        */
+                           (BF16x3 plans: also a multiple of 16)                          */
   int32_t precision;    /* rts_precision                                                 */
   int32_t schedule;     /* rts_schedule: how the FP32 tile kernels are launched           */
 } rts_params;

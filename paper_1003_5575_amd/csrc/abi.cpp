@@ -100,9 +100,11 @@ rts_status validate(const rts_params *p) {
   RTS_REQUIRE(n < ((int64_t)1 << 31), "n_chan*n_base*n_time*(1+conjugate) must be < 2^31");
   RTS_REQUIRE(p->n_grid >= p->support + 2, "n_grid must be at least support + 2");
   if (p->precision == RTS_PREC_BF16X3) {
-    RTS_REQUIRE(p->tile == 0 || p->tile == 16, "BF16x3 plans use 16-cell tiles (got tile %d)", p->tile);
     RTS_REQUIRE(p->n_grid % 16 == 0, "BF16x3 plans need n_grid divisible by 16");
-  } else if (p->tile != 0) {
+    RTS_REQUIRE(p->tile == 0 || p->tile % 16 == 0, "BF16x3 plans need a tile that is a multiple of 16 (got %d)",
+                p->tile);
+  }
+  if (p->tile != 0) {
     RTS_REQUIRE(p->tile >= p->support + 1 && p->tile <= kMaxTile && p->tile % 2 == 0 &&
                     p->n_grid % p->tile == 0,
                 "tile must be even, divide n_grid, and lie in [support+1, %d] (got %d)", kMaxTile,
@@ -370,8 +372,8 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   P->h_lo = (P->W & 1) ? (P->W - 1) / 2 : P->W / 2 - 1;
   P->beta = params->beta > 0.0 ? params->beta : 2.34 * P->W;
   P->precision = params->precision;
-  P->tile = params->precision == RTS_PREC_BF16X3 ? 16 : (params->tile ? params->tile : choose_tile(P->N, P->WN));
-  if (P->tile == 0) {
+  P->tile = params->tile ? params->tile : choose_tile(P->N, P->WN);   // 64, 32 or 16
+  if (P->tile == 0 || (P->precision == RTS_PREC_BF16X3 && P->tile % 16 != 0)) {
     set_error("no legal tile size for n_grid=%d support=%d", P->N, P->W);
     return RTS_E_UNSUPPORTED;
   }

@@ -1,16 +1,22 @@
-// Gridding as a dense per-tile contraction on the matrix cores, with BF16 hi+lo
-// split operands and FP32 accumulation.
+// Gridding and degridding as dense per-tile contractions on the matrix cores,
+// with BF16 hi+lo split operands and FP32 accumulation.
 //
-// For one 16x16-cell tile of one channel, Eq. (1) restricted to the tile is
+// For one 16x16-cell subtile of one channel, Eq. (1) restricted to the subtile is
 //     G_re = Av^T diag(w Re V) Au,   G_im = Av^T diag(w Im V) Au,
-// where Av[s][y] (Au[s][x]) is the kernel weight of sample s on tile row y
-// (column x), zero outside its support.  K runs over the samples whose window
-// touches the tile (the plan's work list), 32 at a time.  Every operand x is
-// split as x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), and the product
-// is taken as hi*hi + hi*lo + lo*hi (three v_mfma_f32_16x16x32_bf16 per output
-// block, FP32 accumulation): about 16 significant bits per operand, relative
-// error of a few 1e-6 on the grid.  The accumulators stay in registers for the
-// whole tile, so there are no atomics; one wave owns one tile.
+// where Av[s][y] (Au[s][x]) is the kernel weight of sample s on subtile row y
+// (column x), zero outside its support; degridding is its adjoint, H = Av G
+// followed by the sum over columns weighted by Au.  Every operand x is split as
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), and each product is taken
+// as hi*hi + hi*lo + lo*hi (three v_mfma_f32_16x16x32_bf16 per block, FP32
+// accumulation): about 16 significant bits per operand, relative error of a few
+// 1e-6.
+//
+// A workgroup owns one tile of the plan (16, 32 or 64 cells, sorted by the
+// plan's counting sort); each of its waves owns one 16x16 subtile and keeps a
+// queue of the tile's listings whose window touches that subtile (ballot
+// compaction), consuming it in chunks of sample slots.  Gridding accumulators
+// stay in registers (no atomics); degridding adds each subtile's partial model
+// values with FP32 atomics.
 #include "internal.h"
 
 namespace rts {
@@ -19,14 +25,15 @@ namespace {
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-constexpr int kMT = 16;          // tile edge of this kernel (one MFMA output block)
-constexpr int kChunk = 32;       // samples per MFMA K step
-constexpr int kWaves = 4;        // tiles (waves) per workgroup
+constexpr int kMT = 16;          // subtile edge (one MFMA output block)
+constexpr int kMaxWaves = (kMaxTile / kMT) * (kMaxTile / kMT);
+constexpr int kQueue = 128;      // listing queue per wave (at most chunk - 1 + 64 entries)
 
 struct SampleSlot {
-  int dx, dy;       // window origin relative to the tile origin (cells)
+  int dx, dy;       // window origin relative to the subtile origin (cells)
   int sx, sy;       // extended-table rows of the sample (-1: no sample)
-  float ar, ai;     // w * V (zero for an empty or invalid slot)
+  float ar, ai;     // w * V (gridding) / unused (degridding)
+  int vi;           // model index (degridding)
 };
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }   // round to nearest even
@@ -37,28 +44,76 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo) {
   lo = to_bf16(x - (float)hi);
 }
 
-__global__ __launch_bounds__(64 * kWaves) void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
-                                                                   const uint16_t *tab_lo) {
-  __shared__ SampleSlot slots[kWaves][kChunk];
+// Table copy into LDS: FP32 rows, then the BF16 hi and lo parts.
+__device__ __forceinline__ void load_tables(const TileArgs &a, const uint16_t *tab_hi, const uint16_t *tab_lo,
+                                            float *&tabE, uint16_t *&thi, uint16_t *&tlo) {
   extern __shared__ float4 smem4[];
-  float *tabE = reinterpret_cast<float *>(smem4);                       // [2*OS][WNP] FP32
-  uint16_t *thi = reinterpret_cast<uint16_t *>(tabE + a.OS2 * a.WNP);   // [2*OS][WNP] bf16 bits
-  uint16_t *tlo = thi + a.OS2 * a.WNP;
-  for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += 64 * kWaves) {
+  tabE = reinterpret_cast<float *>(smem4);
+  thi = reinterpret_cast<uint16_t *>(tabE + a.OS2 * a.WNP);
+  tlo = thi + a.OS2 * a.WNP;
+  for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += blockDim.x) {
     tabE[i] = a.tabE[i];
     thi[i] = tab_hi[i];
     tlo[i] = tab_lo[i];
   }
   __syncthreads();
+}
+
+// Walk the tile's work list and call chunk(n) whenever the wave's queue holds
+// `per_chunk` listings whose window overlaps the subtile at (x0, y0) (and once
+// more for the remainder).  q: the wave's queue; chunk reads q[0..n).
+template <class Chunk>
+__device__ __forceinline__ void for_subtile_chunks(const TileArgs &a, uint32_t beg, uint32_t end, int x0, int y0,
+                                                   bool with_copies, uint32_t *q, int per_chunk, Chunk chunk) {
+  const int lane = threadIdx.x & 63;
+  int qn = 0;                                        // wave-uniform
+  for (uint32_t base = beg; base < end; base += 64) {
+    const uint32_t k = base + (uint32_t)lane;
+    bool ov = false;
+    if (k < end) {
+      const uint2 rec = a.list[k];
+      const bool any = (rec.y >> kRecAnyBit) & 1u;
+      const bool copy = (rec.y >> kRecCopyBit) & 1u;
+      const int X0 = (int)(rec.y & kRecXMask), Y0 = (int)((rec.y >> kRecYShift) & kRecXMask);
+      ov = any && (with_copies || !copy) && X0 < x0 + kMT && X0 + a.WN > x0 && Y0 < y0 + kMT && Y0 + a.WN > y0;
+    }
+    const unsigned long long m = __ballot(ov);
+    const int pos = qn + __popcll(m & ((1ull << lane) - 1ull));
+    if (ov) q[pos] = k;
+    qn += __popcll(m);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    while (qn >= per_chunk) {
+      chunk(per_chunk);
+      const int rest = qn - per_chunk;               // < 64
+      const uint32_t t = lane < rest ? q[per_chunk + lane] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      if (lane < rest) q[lane] = t;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);
+      qn = rest;
+    }
+  }
+  if (qn > 0) chunk(qn);
+}
+
+__global__ __launch_bounds__(64 * kMaxWaves) void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
+                                                                     const uint16_t *tab_lo) {
+  constexpr int kChunk = 32;                         // sample slots per MFMA K step
+  __shared__ SampleSlot slots[kMaxWaves][kChunk];
+  __shared__ uint32_t queue[kMaxWaves][kQueue];
+  float *tabE;
+  uint16_t *thi, *tlo;
+  load_tables(a, tab_hi, tab_lo, tabE, thi, tlo);
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ngroups = (a.nkeys + kWaves - 1) / kWaves;
-  const int key = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave;
-  if (blockIdx.x >= (unsigned)ngroups || key >= a.nkeys) return;   // whole wave leaves together
+  const int nsub = a.tile / kMT;
+  const int key = xcd_remap(blockIdx.x, gridDim.x);
   const int c = key / a.nT2;
   const int rem = key - c * a.nT2;
   const int ty = rem / a.nT, tx = rem - ty * a.nT;
-  const int x0 = tx * kMT, y0 = ty * kMT;
+  const int x0 = tx * a.tile + kMT * (wave % nsub), y0 = ty * a.tile + kMT * (wave / nsub);
   const uint32_t cap = (uint32_t)a.list_cap;
   const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
   const size_t copy_stride = (size_t)a.B * a.T;
@@ -66,25 +121,24 @@ __global__ __launch_bounds__(64 * kWaves) void k_grid_mfma_bf16x3(TileArgs a, co
   f4_t acc_re = {0.0f, 0.0f, 0.0f, 0.0f}, acc_im = {0.0f, 0.0f, 0.0f, 0.0f};
   const int i16 = lane & 15, g = lane >> 4;        // MFMA operand row/column and K group
   SampleSlot *ss = slots[wave];
-
+  uint32_t *q = queue[wave];
   // seg_max (2, 4 or 8) sample slots per listing, kChunk / seg_max listings per chunk
   const int lg = __builtin_ctz((unsigned)a.seg_max);
-  const uint32_t per_chunk = (uint32_t)(kChunk >> lg);
-  for (uint32_t k0 = beg; k0 < end; k0 += per_chunk) {
-    // Stage the chunk: slot lane holds sample (lane mod seg_max) of listing
-    // k0 + lane / seg_max; slots past a segment's end stay empty.
+
+  for_subtile_chunks(a, beg, end, x0, y0, true, q, kChunk >> lg, [&](int n) {
+    // Stage the chunk: slot lane holds sample (lane mod seg_max) of queued listing lane / seg_max.
     if (lane < kChunk) {
       SampleSlot sl;
       sl.dx = sl.dy = 0;
       sl.sx = sl.sy = -1;
       sl.ar = sl.ai = 0.0f;
-      const uint32_t k = k0 + (uint32_t)(lane >> lg);
+      sl.vi = 0;
+      const int li = lane >> lg;
       const int j = lane & (a.seg_max - 1);
-      if (k < end) {
-        const uint2 rec = a.list[k];
+      if (li < n) {
+        const uint2 rec = a.list[q[li]];
         const int nt = (int)((rec.y >> kRecNtShift) & 7u) + 1;
-        const bool any = (rec.y >> kRecAnyBit) & 1u;
-        if (any && j < nt) {
+        if (j < nt) {
           const int copy = (int)((rec.y >> kRecCopyBit) & 1u);
           const size_t vi = rec.x + j;
           const size_t ci = vi + (size_t)(c * (a.ncopy - 1) + copy) * copy_stride;
@@ -138,7 +192,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_grid_mfma_bf16x3(TileArgs a, co
     acc_im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bil, acc_im, 0, 0, 0);
     acc_im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bih, acc_im, 0, 0, 0);
     __builtin_amdgcn_wave_barrier();   // the next chunk's slot writes follow these reads
-  }
+  });
 
   // D[y][x] sits in lane x + 16 * (y / 4), register y % 4.
   float2 *out = a.gout + ((size_t)c * a.N + y0) * a.N + x0;
@@ -149,50 +203,36 @@ __global__ __launch_bounds__(64 * kWaves) void k_grid_mfma_bf16x3(TileArgs a, co
   }
 }
 
-// Degridding of one 16x16 tile on the matrix cores.  For the samples of the
-// tile's work list (16 at a time, rows of the MFMA), H = Av G_tile holds, per
-// sample and tile column x, the sum over the tile's rows of k_y * G; the sample's
-// partial model value over this tile is sum_x H[s][x] k_x(x).  The window of a
-// sample that crosses tile edges is covered by its listings in each tile, so
-// the partial values are added to the (zeroed) model with FP32 atomics.  Both
-// operands of H are split hi+lo as in the gridding kernel; H is formed as one
-// K=32 contraction per term with B = [Re G; Im G] stacked along K and A holding
-// k_y in the half that selects the real or imaginary part.
-struct DegridSlot {
-  int dx, dy;     // window origin relative to the tile origin (cells)
-  int sx, sy;     // extended-table rows (-1: no sample)
-  int vi;         // model index
-};
-
-__global__ __launch_bounds__(64 * kWaves) void k_degrid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
-                                                                     const uint16_t *tab_lo) {
-  __shared__ DegridSlot dslots[kWaves][16];
-  extern __shared__ float4 smem4[];
-  float *tabE = reinterpret_cast<float *>(smem4);
-  uint16_t *thi = reinterpret_cast<uint16_t *>(tabE + a.OS2 * a.WNP);
-  uint16_t *tlo = thi + a.OS2 * a.WNP;
-  for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += 64 * kWaves) {
-    tabE[i] = a.tabE[i];
-    thi[i] = tab_hi[i];
-    tlo[i] = tab_lo[i];
-  }
-  __syncthreads();
+// Degridding of one subtile: for the queued samples (16 at a time, rows of the
+// MFMA), H = Av G_sub holds, per sample and subtile column x, the sum over the
+// subtile's rows of k_y * G; the sample's partial model value over this subtile
+// is sum_x H[s][x] k_x(x).  A window crossing subtile edges is covered by the
+// subtiles it touches, so the partial values are added to the (zeroed) model
+// with FP32 atomics.  H is formed as one K=32 contraction per term with
+// B = [Re G; Im G] stacked along K and A holding k_y in the half that selects
+// the real or imaginary part.
+__global__ __launch_bounds__(64 * kMaxWaves) void k_degrid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
+                                                                       const uint16_t *tab_lo) {
+  constexpr int kChunk = 16;
+  __shared__ SampleSlot dslots[kMaxWaves][kChunk];
+  __shared__ uint32_t queue[kMaxWaves][kQueue];
+  float *tabE;
+  uint16_t *thi, *tlo;
+  load_tables(a, tab_hi, tab_lo, tabE, thi, tlo);
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ngroups = (a.nkeys + kWaves - 1) / kWaves;
-  const int key = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave;
-  if (blockIdx.x >= (unsigned)ngroups || key >= a.nkeys) return;   // whole wave leaves together
+  const int nsub = a.tile / kMT;
+  const int key = xcd_remap(blockIdx.x, gridDim.x);
   const int c = key / a.nT2;
   const int rem = key - c * a.nT2;
   const int ty = rem / a.nT, tx = rem - ty * a.nT;
-  const int x0 = tx * kMT, y0 = ty * kMT;
+  const int x0 = tx * a.tile + kMT * (wave % nsub), y0 = ty * a.tile + kMT * (wave / nsub);
   const uint32_t cap = (uint32_t)a.list_cap;
   const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
-  if (beg >= end) return;
   const int i16 = lane & 15, g = lane >> 4;
 
   // B operand, loaded once: lane (x = i16, g) holds rows 8(g & 1) + e of Re G
-  // (g < 2) or Im G (g >= 2) at tile column x.
+  // (g < 2) or Im G (g >= 2) at subtile column x.
   bf8_t bh, bl;
   {
     const float2 *gt = a.gin + ((size_t)c * a.N + y0) * a.N + x0 + i16;
@@ -205,24 +245,24 @@ __global__ __launch_bounds__(64 * kWaves) void k_degrid_mfma_bf16x3(TileArgs a, 
       bl[e] = l;
     }
   }
-  DegridSlot *ds = dslots[wave];
+  SampleSlot *ds = dslots[wave];
+  uint32_t *q = queue[wave];
   const int lg = __builtin_ctz((unsigned)a.seg_max);
-  const uint32_t per_chunk = (uint32_t)(16 >> lg);
-  for (uint32_t k0 = beg; k0 < end; k0 += per_chunk) {
-    // Stage 16 sample slots: slot j holds sample (j mod seg_max) of listing k0 + j / seg_max.
-    if (lane < 16) {
-      DegridSlot sl;
+
+  for_subtile_chunks(a, beg, end, x0, y0, false, q, kChunk >> lg, [&](int n) {
+    // Stage 16 sample slots: slot j holds sample (j mod seg_max) of queued listing j / seg_max.
+    if (lane < kChunk) {
+      SampleSlot sl;
       sl.dx = sl.dy = 0;
       sl.sx = sl.sy = -1;
+      sl.ar = sl.ai = 0.0f;
       sl.vi = 0;
-      const uint32_t k = k0 + (uint32_t)(lane >> lg);
+      const int li = lane >> lg;
       const int j = lane & (a.seg_max - 1);
-      if (k < end) {
-        const uint2 rec = a.list[k];
+      if (li < n) {
+        const uint2 rec = a.list[q[li]];
         const int nt = (int)((rec.y >> kRecNtShift) & 7u) + 1;
-        const bool any = (rec.y >> kRecAnyBit) & 1u;
-        const int copy = (int)((rec.y >> kRecCopyBit) & 1u);
-        if (any && copy == 0 && j < nt) {
+        if (j < nt) {
           const size_t vi = rec.x + j;
           const uint16_t cw = a.coords[vi + (size_t)(c * (a.ncopy - 1)) * ((size_t)a.B * a.T)];
           if (cw & kCoordValid) {
@@ -239,11 +279,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_degrid_mfma_bf16x3(TileArgs a, 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
 
-    // A operand: lane (s = i16, g) holds k_y of sample s at tile rows 8(g & 1) + e,
+    // A operand: lane (s = i16, g) holds k_y of sample s at subtile rows 8(g & 1) + e,
     // in the real half (g < 2) or the imaginary half (g >= 2) of K.
     bf8_t arh, arl, aih, ail;
     {
-      const DegridSlot sl = ds[i16];
+      const SampleSlot sl = ds[i16];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int ry = 8 * (g & 1) + e - sl.dy;
@@ -270,7 +310,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_degrid_mfma_bf16x3(TileArgs a, 
     // over the 16 columns of a row of lanes.
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const DegridSlot sl = ds[4 * g + r];
+      const SampleSlot sl = ds[4 * g + r];
       const int rx = i16 - sl.dx;
       const bool in = sl.sx >= 0 && rx >= 0 && rx < a.WN;
       const float kx = in ? tabE[sl.sx * a.WNP + rx] : 0.0f;
@@ -286,26 +326,26 @@ __global__ __launch_bounds__(64 * kWaves) void k_degrid_mfma_bf16x3(TileArgs a, 
       }
     }
     __builtin_amdgcn_wave_barrier();   // the next chunk's slot writes follow these reads
-  }
+  });
 }
 
 }  // namespace
 
 hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
-  const int ngroups = (int)((P.nkeys + kWaves - 1) / kWaves);
   const size_t lds = (size_t)a.OS2 * a.WNP * (sizeof(float) + 2 * sizeof(uint16_t));
-  hipLaunchKernelGGL(k_grid_mfma_bf16x3, dim3((unsigned)ngroups), dim3(64 * kWaves), lds, s, a, P.d_tab_hi,
+  const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT));
+  hipLaunchKernelGGL(k_grid_mfma_bf16x3, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
                      P.d_tab_lo);
   return hipGetLastError();
 }
 
 hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
-  // the model is the sum of per-tile partial values: start from zero
+  // the model is the sum of per-subtile partial values: start from zero
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(a.model), (int64_t)2 * P.C * P.B * P.T, 0u, s);
   if (e != hipSuccess) return e;
-  const int ngroups = (int)((P.nkeys + kWaves - 1) / kWaves);
   const size_t lds = (size_t)a.OS2 * a.WNP * (sizeof(float) + 2 * sizeof(uint16_t));
-  hipLaunchKernelGGL(k_degrid_mfma_bf16x3, dim3((unsigned)ngroups), dim3(64 * kWaves), lds, s, a, P.d_tab_hi,
+  const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT));
+  hipLaunchKernelGGL(k_degrid_mfma_bf16x3, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
                      P.d_tab_lo);
   return hipGetLastError();
 }

@@ -32,7 +32,7 @@ def test_bf16x3_grid_error_per_channel(rts, W, OS, N, conj):
                               flag_frac=0.1, offgrid_frac=0.02)
     uvw, vis, w = to_dev(torch, wl)
     plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, conjugate=conj, precision="bf16x3")
-    assert plan.info["tile"] == 16
+    assert plan.info["tile"] % 16 == 0
     G = plan.grid(vis, w).cpu().numpy()
     Gref = O.grid(O.Geometry(wl.uvw_m, freq, wl.weights, N, du, W, OS, conjugate=conj), wl.vis, wl.weights)
     errs = [rel_l2(G[c], Gref[c]) for c in range(len(freq))]
