@@ -7,21 +7,25 @@
 // (column x), zero outside its support; degridding is its adjoint, H = Av G
 // followed by the sum over columns weighted by Au.  Every operand x is split as
 // x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), and each product is taken
-// as hi*hi + hi*lo + lo*hi (three v_mfma_f32_16x16x32_bf16 per block, FP32
-// accumulation): about 16 significant bits per operand, relative error of a few
-// 1e-6.
+// as hi*hi + hi*lo + lo*hi (three MFMAs per block, FP32 accumulation): about 16
+// significant bits per operand, relative error of a few 1e-6.
 //
-// A workgroup owns one tile of the plan (16, 32 or 64 cells, sorted by the
-// plan's counting sort); each of its waves owns one 16x16 subtile and keeps a
-// queue of the tile's listing records whose window touches that subtile (ballot
-// compaction), consuming it in chunks of sample slots.  A slot is 16 bytes in
-// LDS: the window origin relative to the subtile and the two table-row bases as
-// packed 16-bit pairs, then w*V (gridding) or the model index (degridding), so
-// building the MFMA operands is branch-free: one slot read and two table reads
-// per sample and lane.  Gridding accumulators stay in registers (no atomics);
-// degridding reduces each sample's partial value over the subtile columns with
-// DPP and adds it to the (zeroed) model with FP32 atomics, one atomic
-// instruction per chunk.
+// A workgroup owns one tile of the plan (16 to 64 cells, sorted by the plan's
+// counting sort); each of its waves owns a region of one or two 16x16 subtiles
+// and keeps a queue of the tile's listing records whose window touches that
+// region (ballot compaction), consuming it in chunks of sample slots.
+//
+// The kernel tables sit in LDS as zero-padded rows: row r (one phase) holds its
+// WN weights followed by R - 1 zeros, after R leading zeros, where R is the
+// region edge along that axis.  A sample's slot stores the LDS byte address of
+// its table entry for region row (column) 0, so the weight at row y is a plain
+// read at that address + 4y: offsets outside the support land on zeros, and an
+// empty slot points at the leading zeros.  Building the MFMA operands is then
+// reads, packing and (for gridding) the split of w V times the column weight.
+//
+// Gridding accumulators stay in registers (no atomics); degridding reduces each
+// sample's partial value over the region columns with DPP and adds it to the
+// (zeroed) model with FP32 atomics, one atomic instruction per chunk.
 #include "internal.h"
 
 namespace rts {
@@ -31,16 +35,34 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef float f2v_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
 typedef unsigned u4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u2_t __attribute__((ext_vector_type(2)));
 
 constexpr int kMT = 16;          // subtile edge (one MFMA output block)
-constexpr int kMaxWaves = (kMaxTile / kMT) * (kMaxTile / kMT);
 constexpr int kQueue = 128;      // listing queue per wave (at most chunk - 1 + 64 entries)
-constexpr int kFar = 0x4000;     // window offset of an empty slot: every row and column test fails
 
-__device__ __forceinline__ uint32_t pack16(int lo, int hi) { return ((uint32_t)lo & 0xFFFFu) | ((uint32_t)hi << 16); }
-__device__ __forceinline__ int lo16(uint32_t v) { return (int)(v << 16) >> 16; }
-__device__ __forceinline__ int hi16(uint32_t v) { return (int)v >> 16; }
+// Waves per workgroup: one per region; regions of two subtiles when the tile
+// edge is a multiple of 32 (at most 64 / 32 * 64 / 16 = 8), else one subtile
+// (at most (48 / 16)^2 = 9, for tile 48; 16 bounds it).
+template <int NR>
+constexpr int max_waves() { return NR == 2 ? 8 : 16; }
+
+// Padded table geometry for region rows RH and columns RW, in words: FP32
+// weights (the column weights of gridding and degridding) then packed hi|lo
+// BF16 words (the row operand).
+struct PadGeom {
+  int SX, SA;   // row strides: WN + RW - 1 and WN + RH - 1
+  int TX, TA;   // table sizes: RW + OS2 * SX and RH + OS2 * SA
+};
+__host__ __device__ __forceinline__ PadGeom pad_geom(int WN, int OS2, int RH, int RW) {
+  PadGeom p;
+  p.SX = WN + RW - 1;
+  p.SA = WN + RH - 1;
+  p.TX = RW + OS2 * p.SX;
+  p.TA = RH + OS2 * p.SA;
+  return p;
+}
 
 // Two products a0*k0, a1*k1 split into packed BF16 pairs: hi = bf16(p) (round to
 // nearest even), lo = bf16(p - hi) with the residual taken by an FMA.
@@ -60,38 +82,63 @@ __device__ __forceinline__ uint32_t split_one(float x) {
   return h | (l << 16);
 }
 
-// Table copy into LDS: the FP32 rows, then the BF16 hi and lo parts packed as
-// one word per entry (hi in the low half).
-__device__ __forceinline__ void load_tables(const TileArgs &a, const uint16_t *tab_hi, const uint16_t *tab_lo,
-                                            float *&tabE, uint32_t *&thl) {
+// Low halves (hi parts) and high halves (lo parts) of two packed words, as one word.
+__device__ __forceinline__ uint32_t lows(uint32_t w0, uint32_t w1) { return __builtin_amdgcn_perm(w1, w0, 0x05040100u); }
+__device__ __forceinline__ uint32_t highs(uint32_t w0, uint32_t w1) { return __builtin_amdgcn_perm(w1, w0, 0x07060302u); }
+
+// Padded tables into LDS (layout above); returns the LDS base.  Zero the whole
+// area (16-byte stores; the launch rounds it up to whole 16-byte words), then
+// place the WN weights of each phase row, 32 threads per row.
+__device__ __forceinline__ const char *load_padded_tables(const TileArgs &a, const uint16_t *tab_hi,
+                                                          const uint16_t *tab_lo, const PadGeom &pg, int RH,
+                                                          int RW) {
   extern __shared__ float4 smem4[];
-  tabE = reinterpret_cast<float *>(smem4);
-  thl = reinterpret_cast<uint32_t *>(tabE + a.OS2 * a.WNP);
-  for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += blockDim.x) {
-    tabE[i] = a.tabE[i];
-    thl[i] = (uint32_t)tab_hi[i] | ((uint32_t)tab_lo[i] << 16);
+  const int n4 = (pg.TX + pg.TA + 3) >> 2;
+  for (int i = threadIdx.x; i < n4; i += blockDim.x) smem4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  __syncthreads();
+  float *tab = reinterpret_cast<float *>(smem4);
+  uint32_t *thl = reinterpret_cast<uint32_t *>(tab + pg.TX);
+  for (int i = threadIdx.x; i < a.OS2 * 32; i += blockDim.x) {
+    const int r = i >> 5, t = i & 31;
+    if (t < a.WN) {
+      const int src = r * a.WNP + t;
+      tab[RW + r * pg.SX + t] = a.tabE[src];
+      thl[RH + r * pg.SA + t] = (uint32_t)tab_hi[src] | ((uint32_t)tab_lo[src] << 16);
+    }
   }
   __syncthreads();
+  return reinterpret_cast<const char *>(smem4);
+}
+
+__device__ __forceinline__ uint32_t lds_u32(const char *lds, uint32_t byte) {
+  return *reinterpret_cast<const uint32_t *>(lds + byte);
+}
+__device__ __forceinline__ float lds_f32(const char *lds, uint32_t byte) {
+  return *reinterpret_cast<const float *>(lds + byte);
 }
 
 // Walk the tile's listings and call chunk(n) whenever the wave's queue holds
-// `per_chunk` records whose window overlaps the subtile at (x0, y0) (and once
-// more for the remainder).  q: the wave's queue of records; chunk reads q[0..n).
+// `per_chunk` records whose window overlaps the rw x rh region at (x0, y0) (and
+// once more for the remainder).  q: the wave's queue of records; chunk reads
+// q[0..n).  The next 64 records are loaded while the current ones are used.
 template <class Chunk>
 __device__ __forceinline__ void for_subtile_chunks(const TileArgs &a, uint32_t beg, uint32_t end, int x0, int y0,
-                                                   bool with_copies, uint2 *q, int per_chunk, Chunk chunk) {
+                                                   int rw, int rh, bool with_copies, uint2 *q, int per_chunk,
+                                                   Chunk chunk) {
   const int lane = threadIdx.x & 63;
   int qn = 0;                                        // wave-uniform
+  uint2 nrec = make_uint2(0u, 0u);
+  if (beg + (uint32_t)lane < end) nrec = a.list[beg + lane];
   for (uint32_t base = beg; base < end; base += 64) {
     const uint32_t k = base + (uint32_t)lane;
     bool ov = false;
-    uint2 rec = make_uint2(0u, 0u);
+    const uint2 rec = nrec;
+    if (k + 64 < end) nrec = a.list[k + 64];
     if (k < end) {
-      rec = a.list[k];
       const bool any = (rec.y >> kRecAnyBit) & 1u;
       const bool copy = (rec.y >> kRecCopyBit) & 1u;
       const int X0 = (int)(rec.y & kRecXMask), Y0 = (int)((rec.y >> kRecYShift) & kRecXMask);
-      ov = any && (with_copies || !copy) && X0 < x0 + kMT && X0 + a.WN > x0 && Y0 < y0 + kMT && Y0 + a.WN > y0;
+      ov = any && (with_copies || !copy) && X0 < x0 + rw && X0 + a.WN > x0 && Y0 < y0 + rh && Y0 + a.WN > y0;
     }
     const unsigned long long m = __ballot(ov);
     const int pos = qn + __popcll(m & ((1ull << lane) - 1ull));
@@ -114,51 +161,63 @@ __device__ __forceinline__ void for_subtile_chunks(const TileArgs &a, uint32_t b
   if (qn > 0) chunk(qn);
 }
 
-// Slot of sample j of a queued record for the subtile at (x0, y0): .x = window
-// origin (dy, dx) relative to the subtile, .y = table indices minus that origin
-// (sy*WNP - dy, sx*WNP - dx), so that row y of the subtile reads entry .y.lo + y
-// when 0 <= y - dy < WN.  An empty slot has the origin at kFar.
-__device__ __forceinline__ void slot_geometry(const TileArgs &a, uint32_t recy, uint16_t cw, int x0, int y0,
-                                              uint32_t &sx_word, uint32_t &sy_word) {
+// LDS byte addresses of a sample's table entries for region row 0 (packed hi|lo
+// row weights) and region column 0 (FP32 column weights).  The queue filter
+// keeps dy in [-(WN-1), RH-1] and dx in [-(WN-1), RW-1], so every read at
+// + 4y (y < RH) or + 4x (x < RW) stays inside the sample's padded row.
+__device__ __forceinline__ void slot_addresses(const TileArgs &a, const PadGeom &pg, int RH, int RW, uint32_t recy,
+                                               uint16_t cw, int x0, int y0, uint32_t &ya, uint32_t &xa) {
   const int dx = (int)(recy & kRecXMask) - x0;
   const int dy = (int)((recy >> kRecYShift) & kRecXMask) - y0;
   const int sx = cw & 0x7F, sy = (cw >> 7) & 0x7F;
-  sx_word = pack16(dy, dx);
-  sy_word = pack16(sy * a.WNP - dy, sx * a.WNP - dx);
+  ya = 4u * (uint32_t)(pg.TX + RH + sy * pg.SA - dy);
+  xa = 4u * (uint32_t)(RW + sx * pg.SX - dx);
 }
 
-__global__ __launch_bounds__(64 * kMaxWaves) void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
-                                                                     const uint16_t *tab_lo) {
+// Gridding of a region of GR x 1 subtiles (16 GR rows, 16 columns): the B
+// operand (w V times the column weights, the costlier one to build) is shared
+// by the GR row blocks.  One v_mfma_f32_16x16x32_bf16 per term and block: K
+// runs over 32 sample slots.  Registers are capped at 80 so that three
+// workgroups of 8 waves share a CU.
+template <int GR>
+__global__ __launch_bounds__(64 * max_waves<GR>()) __attribute__((amdgpu_waves_per_eu(6)))
+void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
+                                                                           const uint16_t *tab_lo) {
   constexpr int kChunk = 32;                         // sample slots per MFMA K step
-  __shared__ uint4 slots[kMaxWaves][kChunk];
-  __shared__ uint2 queue[kMaxWaves][kQueue];
-  float *tabE;
-  uint32_t *thl;
-  load_tables(a, tab_hi, tab_lo, tabE, thl);
+  constexpr int RH = GR * kMT, RW = kMT;
+  __shared__ uint4 slots[max_waves<GR>()][kChunk];
+  __shared__ uint2 queue[max_waves<GR>()][kQueue];
+  const PadGeom pg = pad_geom(a.WN, a.OS2, RH, RW);
+  const char *lds = load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
 
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nsub = a.tile / kMT;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int nwx = a.tile / RW;                      // regions per tile row
   const int key = xcd_remap(blockIdx.x, gridDim.x);
   const int c = key / a.nT2;
   const int rem = key - c * a.nT2;
   const int ty = rem / a.nT, tx = rem - ty * a.nT;
-  const int x0 = tx * a.tile + kMT * (wave % nsub), y0 = ty * a.tile + kMT * (wave / nsub);
+  const int x0 = tx * a.tile + RW * (wave % nwx), y0 = ty * a.tile + RH * (wave / nwx);
   const uint32_t cap = (uint32_t)a.list_cap;
   const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
   const size_t copy_stride = (size_t)a.B * a.T;
-  const unsigned WN = (unsigned)a.WN;
+  const uint32_t empty_ya = 4u * (uint32_t)pg.TX, empty_xa = 0u;
 
-  f4_t acc_re = {0.0f, 0.0f, 0.0f, 0.0f}, acc_im = {0.0f, 0.0f, 0.0f, 0.0f};
+  f4_t acc_re[GR], acc_im[GR];
+#pragma unroll
+  for (int rb = 0; rb < GR; ++rb) {
+    acc_re[rb] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    acc_im[rb] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  }
   const int i16 = lane & 15, g = lane >> 4;        // MFMA operand row/column and K group
   uint4 *ss = slots[wave];
   uint2 *q = queue[wave];
   // seg_max (2, 4 or 8) sample slots per listing, kChunk / seg_max listings per chunk
   const int lg = __builtin_ctz((unsigned)a.seg_max);
 
-  for_subtile_chunks(a, beg, end, x0, y0, true, q, kChunk >> lg, [&](int n) {
+  for_subtile_chunks(a, beg, end, x0, y0, RW, RH, true, q, kChunk >> lg, [&](int n) {
     // Stage the chunk: slot lane holds sample (lane mod seg_max) of queued record lane / seg_max.
     if (lane < kChunk) {
-      uint4 sl = make_uint4(pack16(kFar, kFar), 0u, 0u, 0u);
+      uint4 sl = make_uint4(empty_ya, empty_xa, 0u, 0u);
       const int li = lane >> lg;
       const int j = lane & (a.seg_max - 1);
       if (li < n) {
@@ -171,11 +230,11 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_grid_mfma_bf16x3(TileArgs a,
           const uint16_t cw = a.coords[ci];
           const float2 v = a.vis[vi];
           const float wt = a.w[vi];
-          uint32_t gx, gy;
-          slot_geometry(a, rec.y, cw, x0, y0, gx, gy);
+          uint32_t ya, xa;
+          slot_addresses(a, pg, RH, RW, rec.y, cw, x0, y0, ya, xa);
           const bool ok = (cw & kCoordValid) != 0;
-          sl.x = ok ? gx : sl.x;
-          sl.y = ok ? gy : 0u;
+          sl.x = ok ? ya : empty_ya;
+          sl.y = ok ? xa : empty_xa;
           sl.z = ok ? __float_as_uint(wt * v.x) : 0u;
           sl.w = ok ? __float_as_uint(copy ? -(wt * v.y) : wt * v.y) : 0u;
         }
@@ -185,27 +244,28 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_grid_mfma_bf16x3(TileArgs a,
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
 
-    // Operands.  A[y][s] = ky_s(y0 + y), row y = i16, samples s = 8g + e.
+    // Operands.  A_rb[y][s] = ky_s(y0 + 16 rb + y), row y = i16, samples s = 8g + e.
     // B[s][x] = a_s kx_s(x0 + x), column x = i16, the same samples.
-    u4_t ah, al, brh, brl, bih, bil;
+    u4_t ah[GR], al[GR], brh, brl, bih, bil;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      uint32_t av[2];
+      uint32_t av[GR][2];
       float kx[2], ar[2], ai[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const uint4 sl = ss[8 * g + 2 * p + h];
-        const int ry = i16 - lo16(sl.x), rx = i16 - hi16(sl.x);
-        const bool iny = (unsigned)ry < WN, inx = (unsigned)rx < WN;
-        const uint32_t t = thl[iny ? lo16(sl.y) + i16 : 0];
-        const float k = tabE[inx ? hi16(sl.y) + i16 : 0];
-        av[h] = iny ? t : 0u;
-        kx[h] = inx ? k : 0.0f;
+        const uint32_t ya = sl.x + 4u * i16, xa = sl.y + 4u * i16;
+#pragma unroll
+        for (int rb = 0; rb < GR; ++rb) av[rb][h] = lds_u32(lds, ya + 4u * kMT * rb);
+        kx[h] = lds_f32(lds, xa);
         ar[h] = __uint_as_float(sl.z);
         ai[h] = __uint_as_float(sl.w);
       }
-      ah[p] = __builtin_amdgcn_perm(av[1], av[0], 0x05040100u);
-      al[p] = __builtin_amdgcn_perm(av[1], av[0], 0x07060302u);
+#pragma unroll
+      for (int rb = 0; rb < GR; ++rb) {
+        ah[rb][p] = lows(av[rb][0], av[rb][1]);
+        al[rb][p] = highs(av[rb][0], av[rb][1]);
+      }
       uint32_t hh, ll;
       split_pair(ar[0], kx[0], ar[1], kx[1], hh, ll);
       brh[p] = hh;
@@ -214,24 +274,30 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_grid_mfma_bf16x3(TileArgs a,
       bih[p] = hh;
       bil[p] = ll;
     }
-    const bf8_t Ah = __builtin_bit_cast(bf8_t, ah), Al = __builtin_bit_cast(bf8_t, al);
     const bf8_t Brh = __builtin_bit_cast(bf8_t, brh), Brl = __builtin_bit_cast(bf8_t, brl);
     const bf8_t Bih = __builtin_bit_cast(bf8_t, bih), Bil = __builtin_bit_cast(bf8_t, bil);
-    acc_re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Brh, acc_re, 0, 0, 0);
-    acc_re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Brl, acc_re, 0, 0, 0);
-    acc_re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Brh, acc_re, 0, 0, 0);
-    acc_im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bih, acc_im, 0, 0, 0);
-    acc_im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bil, acc_im, 0, 0, 0);
-    acc_im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bih, acc_im, 0, 0, 0);
+#pragma unroll
+    for (int rb = 0; rb < GR; ++rb) {
+      const bf8_t Ah = __builtin_bit_cast(bf8_t, ah[rb]), Al = __builtin_bit_cast(bf8_t, al[rb]);
+      acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Brh, acc_re[rb], 0, 0, 0);
+      acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Brl, acc_re[rb], 0, 0, 0);
+      acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Brh, acc_re[rb], 0, 0, 0);
+      acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bih, acc_im[rb], 0, 0, 0);
+      acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bil, acc_im[rb], 0, 0, 0);
+      acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bih, acc_im[rb], 0, 0, 0);
+    }
     __builtin_amdgcn_wave_barrier();   // the next chunk's slot writes follow these reads
   });
 
-  // D[y][x] sits in lane x + 16 * (y / 4), register y % 4.
+  // D[y][x] of row block rb sits in lane x + 16 * (y / 4), register y % 4.
   float2 *out = a.gout + ((size_t)c * a.N + y0) * a.N + x0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int y = 4 * g + r;
-    out[(size_t)y * a.N + i16] = make_float2(acc_re[r], acc_im[r]);
+  for (int rb = 0; rb < GR; ++rb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int y = kMT * rb + 4 * g + r;
+      out[(size_t)y * a.N + i16] = make_float2(acc_re[rb][r], acc_im[rb][r]);
+    }
   }
 }
 
@@ -250,62 +316,63 @@ __device__ __forceinline__ float dpp_xor1(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
 }
 
-// Degridding of one subtile: for the queued samples (16 at a time, rows of the
-// MFMA), H = Av G_sub holds, per sample and subtile column x, the sum over the
-// subtile's rows of k_y * G; the sample's partial model value over this subtile
-// is sum_x H[s][x] k_x(x).  A window crossing subtile edges is covered by the
-// subtiles it touches, so the partial values are added to the (zeroed) model
-// with FP32 atomics.  H is formed as one K=32 contraction per term with
-// B = [Re G; Im G] stacked along K and A holding k_y in the half that selects
-// the real or imaginary part.
-__global__ __launch_bounds__(64 * kMaxWaves) void k_degrid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
-                                                                       const uint16_t *tab_lo) {
+// Degridding of a region of 1 x DC subtiles (16 rows, 16 DC columns): for the
+// queued samples (16 at a time, rows of the MFMA), H = Av G holds, per sample
+// and region column x, the sum over the region's rows of k_y * G, formed with
+// v_mfma_f32_16x16x16_bf16 (K = the 16 rows) separately for Re G and Im G; the
+// A operand (k_y) is shared by the DC column blocks.  The sample's partial
+// model value over the region is sum_x H[s][x] k_x(x).  A window crossing
+// region edges is covered by every region it touches, so the partial values are
+// added to the (zeroed) model with FP32 atomics.
+template <int DC>
+__global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
+                                                                             const uint16_t *tab_lo) {
   constexpr int kChunk = 16;
-  __shared__ uint4 dslots[kMaxWaves][kChunk];
-  __shared__ uint2 queue[kMaxWaves][kQueue];
-  float *tabE;
-  uint32_t *thl;
-  load_tables(a, tab_hi, tab_lo, tabE, thl);
+  constexpr int RH = kMT, RW = DC * kMT;
+  __shared__ uint4 dslots[max_waves<DC>()][kChunk];
+  __shared__ uint2 queue[max_waves<DC>()][kQueue];
+  const PadGeom pg = pad_geom(a.WN, a.OS2, RH, RW);
+  const char *lds = load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nsub = a.tile / kMT;
+  const int nwx = a.tile / RW;                      // regions per tile row
   const int key = xcd_remap(blockIdx.x, gridDim.x);
   const int c = key / a.nT2;
   const int rem = key - c * a.nT2;
   const int ty = rem / a.nT, tx = rem - ty * a.nT;
-  const int x0 = tx * a.tile + kMT * (wave % nsub), y0 = ty * a.tile + kMT * (wave / nsub);
+  const int x0 = tx * a.tile + RW * (wave % nwx), y0 = ty * a.tile + RH * (wave / nwx);
   const uint32_t cap = (uint32_t)a.list_cap;
   const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
   const int i16 = lane & 15, g = lane >> 4;
-  const unsigned WN = (unsigned)a.WN;
+  const uint32_t empty_ya = 4u * (uint32_t)pg.TX, empty_xa = 0u;
 
-  // B operand, loaded once: lane (x = i16, g) holds rows 8(g & 1) + e of Re G
-  // (g < 2) or Im G (g >= 2) at subtile column x.
-  bf8_t bh, bl;
-  {
-    const float2 *gt = a.gin + ((size_t)c * a.N + y0) * a.N + x0 + i16;
-    u4_t h4, l4;
+  // B operands, loaded once: lane (x = i16, g) of block cb holds rows 4g + e of
+  // Re G and Im G at region column 16 cb + x, split into hi and lo parts.
+  s4_t brh[DC], brl[DC], bih[DC], bil[DC];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const float2 v0 = gt[(size_t)(8 * (g & 1) + 2 * p) * a.N];
-      const float2 v1 = gt[(size_t)(8 * (g & 1) + 2 * p + 1) * a.N];
-      const uint32_t s0 = split_one(g < 2 ? v0.x : v0.y), s1 = split_one(g < 2 ? v1.x : v1.y);
-      h4[p] = __builtin_amdgcn_perm(s1, s0, 0x05040100u);
-      l4[p] = __builtin_amdgcn_perm(s1, s0, 0x07060302u);
+  for (int cb = 0; cb < DC; ++cb) {
+    const float2 *gt = a.gin + ((size_t)c * a.N + y0 + 4 * g) * a.N + x0 + kMT * cb + i16;
+    uint32_t sr[4], si[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float2 v = gt[(size_t)e * a.N];
+      sr[e] = split_one(v.x);
+      si[e] = split_one(v.y);
     }
-    bh = __builtin_bit_cast(bf8_t, h4);
-    bl = __builtin_bit_cast(bf8_t, l4);
+    brh[cb] = __builtin_bit_cast(s4_t, u2_t{lows(sr[0], sr[1]), lows(sr[2], sr[3])});
+    brl[cb] = __builtin_bit_cast(s4_t, u2_t{highs(sr[0], sr[1]), highs(sr[2], sr[3])});
+    bih[cb] = __builtin_bit_cast(s4_t, u2_t{lows(si[0], si[1]), lows(si[2], si[3])});
+    bil[cb] = __builtin_bit_cast(s4_t, u2_t{highs(si[0], si[1]), highs(si[2], si[3])});
   }
   uint4 *ds = dslots[wave];
   uint2 *q = queue[wave];
   const int lg = __builtin_ctz((unsigned)a.seg_max);
   const int b3 = (i16 >> 3) & 1, b2 = (i16 >> 2) & 1, b1 = (i16 >> 1) & 1;
-  const uint32_t re_mask = g < 2 ? 0xFFFFFFFFu : 0u;   // K half of this lane: real (g < 2) or imaginary
 
-  for_subtile_chunks(a, beg, end, x0, y0, false, q, kChunk >> lg, [&](int n) {
+  for_subtile_chunks(a, beg, end, x0, y0, RW, RH, false, q, kChunk >> lg, [&](int n) {
     // Stage 16 sample slots: slot j holds sample (j mod seg_max) of queued record j / seg_max.
     if (lane < kChunk) {
-      uint4 sl = make_uint4(pack16(kFar, kFar), 0u, 0xFFFFFFFFu, 0u);
+      uint4 sl = make_uint4(empty_ya, empty_xa, 0xFFFFFFFFu, 0u);
       const int li = lane >> lg;
       const int j = lane & (a.seg_max - 1);
       if (li < n) {
@@ -314,11 +381,11 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_degrid_mfma_bf16x3(TileArgs 
         if (j < nt) {
           const size_t vi = rec.x + j;
           const uint16_t cw = a.coords[vi + (size_t)(c * (a.ncopy - 1)) * ((size_t)a.B * a.T)];
-          uint32_t gx, gy;
-          slot_geometry(a, rec.y, cw, x0, y0, gx, gy);
+          uint32_t ya, xa;
+          slot_addresses(a, pg, RH, RW, rec.y, cw, x0, y0, ya, xa);
           const bool ok = (cw & kCoordValid) != 0;
-          sl.x = ok ? gx : sl.x;
-          sl.y = ok ? gy : 0u;
+          sl.x = ok ? ya : empty_ya;
+          sl.y = ok ? xa : empty_xa;
           sl.z = ok ? (uint32_t)vi : 0xFFFFFFFFu;
         }
       }
@@ -327,55 +394,45 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_degrid_mfma_bf16x3(TileArgs 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
 
-    // A operand: lane (s = i16, g) holds k_y of sample s at subtile rows 8(g & 1) + e,
-    // in the real half (g < 2) or the imaginary half (g >= 2) of K.
-    u4_t rh, rl, ih, il;
+    // A operand: lane (s = i16, g) holds k_y of sample s at region rows 4g + e.
+    s4_t ah, al;
     {
-      const uint4 sl = ds[i16];
-      const int dy = lo16(sl.x), yb = lo16(sl.y);
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        uint32_t av[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int y = 8 * (g & 1) + 2 * p + h;
-          const bool in = (unsigned)(y - dy) < WN;
-          const uint32_t t = thl[in ? yb + y : 0];
-          av[h] = in ? t : 0u;
-        }
-        const uint32_t hp = __builtin_amdgcn_perm(av[1], av[0], 0x05040100u);
-        const uint32_t lp = __builtin_amdgcn_perm(av[1], av[0], 0x07060302u);
-        rh[p] = hp & re_mask;
-        rl[p] = lp & re_mask;
-        ih[p] = hp & ~re_mask;
-        il[p] = lp & ~re_mask;
-      }
+      const uint32_t ya = ds[i16].x + 16u * g;
+      const uint32_t t0 = lds_u32(lds, ya), t1 = lds_u32(lds, ya + 4u);
+      const uint32_t t2 = lds_u32(lds, ya + 8u), t3 = lds_u32(lds, ya + 12u);
+      ah = __builtin_bit_cast(s4_t, u2_t{lows(t0, t1), lows(t2, t3)});
+      al = __builtin_bit_cast(s4_t, u2_t{highs(t0, t1), highs(t2, t3)});
     }
-    const bf8_t arh = __builtin_bit_cast(bf8_t, rh), arl = __builtin_bit_cast(bf8_t, rl);
-    const bf8_t aih = __builtin_bit_cast(bf8_t, ih), ail = __builtin_bit_cast(bf8_t, il);
-    f4_t hr = {0.0f, 0.0f, 0.0f, 0.0f}, hi = {0.0f, 0.0f, 0.0f, 0.0f};
-    hr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bh, hr, 0, 0, 0);
-    hr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arh, bl, hr, 0, 0, 0);
-    hr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bh, hr, 0, 0, 0);
-    hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bh, hi, 0, 0, 0);
-    hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aih, bl, hi, 0, 0, 0);
-    hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bh, hi, 0, 0, 0);
+    f4_t hr[DC], hi[DC];
+#pragma unroll
+    for (int cb = 0; cb < DC; ++cb) {
+      const f4_t z = {0.0f, 0.0f, 0.0f, 0.0f};
+      hr[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, brh[cb], z, 0, 0, 0);
+      hr[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, brl[cb], hr[cb], 0, 0, 0);
+      hr[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, brh[cb], hr[cb], 0, 0, 0);
+      hi[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bih[cb], z, 0, 0, 0);
+      hi[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bil[cb], hi[cb], 0, 0, 0);
+      hi[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bih[cb], hi[cb], 0, 0, 0);
+    }
 
-    // H[s][x] sits in lane x + 16 (s / 4), register s % 4.  Weight by k_x, then
-    // sum the 8 values v[2r + part] over the 16 columns of a lane row by halving
-    // exchanges (mirror, half mirror, xor 2, xor 1): afterwards lane x holds the
-    // sum of value 4 b3 + 2 b2 + b1 (bits of x), i.e. sample 4g + 2 b3 + b2, part b1.
+    // H_cb[s][x] sits in lane x + 16 (s / 4), register s % 4.  Weight by k_x and
+    // add the column blocks, then sum the 8 values v[2r + part] over the 16
+    // columns of a lane row by halving exchanges (mirror, half mirror, xor 2,
+    // xor 1): afterwards lane x holds the sum of value 4 b3 + 2 b2 + b1 (bits of
+    // x), i.e. sample 4g + 2 b3 + b2, part b1.
     float v[8];
     uint32_t vis_r[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const uint4 sl = ds[4 * g + r];
-      const int rx = i16 - hi16(sl.x);
-      const bool in = (unsigned)rx < WN;
-      const float k = tabE[in ? hi16(sl.y) + i16 : 0];
-      const float kx = in ? k : 0.0f;
-      v[2 * r] = hr[r] * kx;
-      v[2 * r + 1] = hi[r] * kx;
+      const uint32_t xa = sl.y + 4u * i16;
+      v[2 * r] = v[2 * r + 1] = 0.0f;
+#pragma unroll
+      for (int cb = 0; cb < DC; ++cb) {
+        const float kx = lds_f32(lds, xa + 4u * kMT * cb);
+        v[2 * r] += hr[cb][r] * kx;
+        v[2 * r + 1] += hi[cb][r] * kx;
+      }
       vis_r[r] = sl.z;
     }
     float u[4];
@@ -398,24 +455,40 @@ __global__ __launch_bounds__(64 * kMaxWaves) void k_degrid_mfma_bf16x3(TileArgs 
   });
 }
 
+size_t padded_lds_bytes(const TileArgs &a, int RH, int RW) {
+  const PadGeom pg = pad_geom(a.WN, a.OS2, RH, RW);
+  return (size_t)16 * (size_t)((pg.TX + pg.TA + 3) / 4);
+}
+
 }  // namespace
 
+// Regions of two subtiles per wave where the tile edge is a multiple of 32.
 hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
-  const size_t lds = (size_t)a.OS2 * a.WNP * (sizeof(float) + sizeof(uint32_t));
-  const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT));
-  hipLaunchKernelGGL(k_grid_mfma_bf16x3, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
-                     P.d_tab_lo);
+  const int pair = P.tile % (2 * kMT) == 0 ? 2 : 1;
+  const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT) / pair);
+  const size_t lds = padded_lds_bytes(a, pair * kMT, kMT);
+  if (pair == 2)
+    hipLaunchKernelGGL(k_grid_mfma_bf16x3<2>, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
+                       P.d_tab_lo);
+  else
+    hipLaunchKernelGGL(k_grid_mfma_bf16x3<1>, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
+                       P.d_tab_lo);
   return hipGetLastError();
 }
 
 hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
-  // the model is the sum of per-subtile partial values: start from zero
+  // the model is the sum of per-region partial values: start from zero
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(a.model), (int64_t)2 * P.C * P.B * P.T, 0u, s);
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)a.OS2 * a.WNP * (sizeof(float) + sizeof(uint32_t));
-  const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT));
-  hipLaunchKernelGGL(k_degrid_mfma_bf16x3, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
-                     P.d_tab_lo);
+  const int pair = P.tile % (2 * kMT) == 0 ? 2 : 1;
+  const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT) / pair);
+  const size_t lds = padded_lds_bytes(a, kMT, pair * kMT);
+  if (pair == 2)
+    hipLaunchKernelGGL(k_degrid_mfma_bf16x3<2>, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
+                       P.d_tab_lo);
+  else
+    hipLaunchKernelGGL(k_degrid_mfma_bf16x3<1>, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
+                       P.d_tab_lo);
   return hipGetLastError();
 }
 

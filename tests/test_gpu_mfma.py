@@ -62,6 +62,47 @@ def test_bf16x3_degrid_error_per_channel(rts, W, OS, N):
     assert max(errs) <= BF16X3_RTOL
 
 
+@pytest.mark.parametrize("tile", [16, 32, 48, 64])
+def test_bf16x3_every_tile_edge(rts, tile):
+    """Tiles of one, two and three subtiles per edge: a wave covers one subtile
+    (tile 16, 48) or a pair of them (tile 32, 64); grid and degrid both."""
+    N, W, OS = 192, 7, 8
+    wl, freq, du = small_case(n_ant=40, channels=(0, 20), N=N, W=W, OS=OS, flag_frac=0.1, offgrid_frac=0.02)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, tile=tile, precision="bf16x3")
+    assert plan.info["tile"] == tile
+    geom = O.Geometry(wl.uvw_m, freq, wl.weights, N, du, W, OS)
+    G = plan.grid(vis, w).cpu().numpy()
+    Gref = O.grid(geom, wl.vis, wl.weights)
+    rng = np.random.default_rng(tile)
+    Gin = (rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))).astype(np.complex64)
+    M = plan.degrid(torch.from_numpy(Gin).cuda()).cpu().numpy()
+    Mref = O.degrid(geom, Gin.astype(np.complex128))
+    for c in range(2):
+        assert rel_l2(G[c], Gref[c]) <= BF16X3_RTOL
+        assert rel_l2(M[c], Mref[c]) <= BF16X3_RTOL
+
+
+@pytest.mark.parametrize("tile", [48, 64])
+def test_bf16x3_widest_tables(rts, tile):
+    """The largest support and oversampling (W=16, OS=64): the zero-padded kernel
+    tables in LDS are at their largest."""
+    N, W, OS = 192, 16, 64
+    wl, freq, du = small_case(n_ant=40, channels=(5, 25), N=N, W=W, OS=OS, flag_frac=0.1, offgrid_frac=0.02)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, tile=tile, precision="bf16x3")
+    geom = O.Geometry(wl.uvw_m, freq, wl.weights, N, du, W, OS)
+    G = plan.grid(vis, w).cpu().numpy()
+    Gref = O.grid(geom, wl.vis, wl.weights)
+    rng = np.random.default_rng(tile + 1)
+    Gin = (rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))).astype(np.complex64)
+    M = plan.degrid(torch.from_numpy(Gin).cuda()).cpu().numpy()
+    Mref = O.degrid(geom, Gin.astype(np.complex128))
+    for c in range(2):
+        assert rel_l2(G[c], Gref[c]) <= BF16X3_RTOL
+        assert rel_l2(M[c], Mref[c]) <= BF16X3_RTOL
+
+
 def test_bf16x3_degrid_is_adjoint_of_bf16x3_grid(rts):
     """<grid(V), G> = <V, degrid(G)> (unit weights) within the BF16x3 error."""
     N = 256
