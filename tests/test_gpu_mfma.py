@@ -44,21 +44,23 @@ def test_bf16x3_grid_error_per_channel(rts, W, OS, N, conj):
     assert max(rel_l2(G32[c], Gref[c]) for c in range(len(freq))) < min(errs)
 
 
-@pytest.mark.parametrize("W,OS,N", [(7, 8, 256), (16, 16, 256), (8, 4, 128), (5, 8, 64)])
-def test_bf16x3_degrid_error_per_channel(rts, W, OS, N):
-    """Degridding as H = Av G_tile on the matrix cores, per-tile partial values
-    summed into the model: error per channel against the FP64 oracle."""
+@pytest.mark.parametrize("W,OS,N,conj", [(7, 8, 256, False), (16, 16, 256, False), (8, 4, 128, False),
+                                         (5, 8, 64, False), (7, 8, 256, True), (16, 16, 256, True)])
+def test_bf16x3_degrid_error_per_channel(rts, W, OS, N, conj):
+    """Degridding as H = Av G_tile on the matrix cores, per-region partial values
+    summed into the model: error per channel against the FP64 oracle (with the
+    conjugate copies listed, degridding reads the +uv samples only)."""
     wl, freq, du = small_case(n_ant=48, channels=(0, 11, 31), N=N, W=W, OS=OS, flag_frac=0.1, offgrid_frac=0.02)
     uvw, vis, w = to_dev(torch, wl)
-    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, precision="bf16x3")
+    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, conjugate=conj, precision="bf16x3")
     rng = np.random.default_rng(W)
     Gin = (rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N))).astype(np.complex64)
     M = plan.degrid(torch.from_numpy(Gin).cuda()).cpu().numpy()
-    geom = O.Geometry(wl.uvw_m, freq, wl.weights, N, du, W, OS)
+    geom = O.Geometry(wl.uvw_m, freq, wl.weights, N, du, W, OS, conjugate=conj)
     Mref = O.degrid(geom, Gin.astype(np.complex128))
     assert np.all(M[~geom.valid] == 0)
     errs = [rel_l2(M[c], Mref[c]) for c in range(len(freq))]
-    print(f"BF16x3 degrid W={W} OS={OS} N={N}: per-channel rel L2 {['%.2e' % e for e in errs]}")
+    print(f"BF16x3 degrid W={W} OS={OS} N={N} conj={conj}: per-channel rel L2 {['%.2e' % e for e in errs]}")
     assert max(errs) <= BF16X3_RTOL
 
 
