@@ -307,3 +307,24 @@ def direct_dft(xs_snapped, ys_snapped, a, N, OS, region):
         ph = 2.0 * np.pi * (xq * (qx - N / 2) + yq * (qy - N / 2)) / N
         out[k] = np.sum(a * np.exp(1j * ph))
     return out
+
+
+# ------------------------------------------------------- polarisation conversion
+def polconvert(A, P) -> np.ndarray:
+    """Section 3, the polarisation convertor stage: for every pixel i, S_i = A_i P_i,
+    where P_i holds the four observed polarisation products of the pixel, A_i is a
+    4x4 complex matrix (supplied by a precomputation) and S_i the converted vector.
+
+    A: complex [4][4][n_pix], one matrix per pixel shared by every channel, or
+    [C][4][4][n_pix], one per channel and pixel.  P: complex [C][4][n_pix].
+    Returns complex128 S [C][4][n_pix] with S[c][r][i] = sum_k A[r][k][i] P[c][k][i]."""
+    P = np.asarray(P, np.complex128)
+    A = np.asarray(A, np.complex128)
+    C = P.shape[0]
+    S = np.zeros(P.shape, np.complex128)
+    for c in range(C):
+        Ac = A if A.ndim == 3 else A[c]
+        for r in range(4):
+            for k in range(4):
+                S[c, r] += Ac[r, k] * P[c, k]
+    return S

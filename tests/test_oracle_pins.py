@@ -354,3 +354,68 @@ def test_grid_vjp_matches_finite_differences():
         wm = w.copy(); wm[0, b, 0] -= 1e-4
         fd = (L2(ww=wp) - L2(ww=wm)) / 2e-4
         assert fd == pytest.approx(gw[0, b, 0], rel=1e-6, abs=1e-7)
+
+
+# ------------------------------------------------------- polarisation conversion
+def _stokes_to_linear(I, Q, U, V):
+    """Observed products of ideal linear feeds: XX = I + Q, XY = U + iV,
+    YX = U - iV, YY = I - Q (the textbook relation, independent of the oracle)."""
+    return np.stack([I + Q, U + 1j * V, U - 1j * V, I - Q])
+
+
+def test_polconvert_identity_returns_input():
+    rng = np.random.default_rng(11)
+    P = rng.standard_normal((3, 4, 37)) + 1j * rng.standard_normal((3, 4, 37))
+    A = np.zeros((4, 4, 37), np.complex128)
+    for r in range(4):
+        A[r, r] = 1.0
+    assert np.array_equal(O.polconvert(A, P), P)
+
+
+def test_polconvert_recovers_stokes_from_linear_feeds():
+    """A = the inverse of the linear-feed relation, written row by row:
+    I = (XX + YY)/2, Q = (XX - YY)/2, U = (XY + YX)/2, V = -i (XY - YX)/2.
+    The matrix is not symmetric, so a transposed operand fails here."""
+    rng = np.random.default_rng(12)
+    n = 50
+    stokes = [rng.standard_normal(n) + 1j * rng.standard_normal(n) for _ in range(4)]
+    P = _stokes_to_linear(*stokes)[None]
+    M = np.array([[0.5, 0, 0, 0.5], [0.5, 0, 0, -0.5], [0, 0.5, 0.5, 0], [0, -0.5j, 0.5j, 0]])
+    A = np.repeat(M[:, :, None], n, axis=2)
+    S = O.polconvert(A, P)
+    for r in range(4):
+        np.testing.assert_allclose(S[0, r], stokes[r], rtol=0, atol=1e-14)
+
+
+def test_polconvert_composition_and_per_channel_matrices():
+    """Converting with B after A equals converting once with the per-pixel
+    product B A (formed by explicit loops); per-channel matrices (c+1) I scale
+    channel c by c+1; a shared matrix equals the same matrix given per channel."""
+    rng = np.random.default_rng(13)
+    n, C = 9, 3
+    A = rng.standard_normal((4, 4, n)) + 1j * rng.standard_normal((4, 4, n))
+    B = rng.standard_normal((4, 4, n)) + 1j * rng.standard_normal((4, 4, n))
+    P = rng.standard_normal((C, 4, n)) + 1j * rng.standard_normal((C, 4, n))
+    BA = np.zeros((4, 4, n), np.complex128)
+    for i in range(n):
+        for r in range(4):
+            for k in range(4):
+                BA[r, k, i] = sum(B[r, m, i] * A[m, k, i] for m in range(4))
+    np.testing.assert_allclose(O.polconvert(B, O.polconvert(A, P)), O.polconvert(BA, P), rtol=1e-12, atol=1e-12)
+    Ac = np.zeros((C, 4, 4, n), np.complex128)
+    for c in range(C):
+        for r in range(4):
+            Ac[c, r, r] = c + 1
+    S = O.polconvert(Ac, P)
+    for c in range(C):
+        np.testing.assert_array_equal(S[c], (c + 1) * P[c])
+    np.testing.assert_array_equal(O.polconvert(np.stack([A] * C), P), O.polconvert(A, P))
+
+
+def test_polconvert_pixels_are_independent():
+    rng = np.random.default_rng(14)
+    n = 21
+    A = rng.standard_normal((4, 4, n)) + 1j * rng.standard_normal((4, 4, n))
+    P = rng.standard_normal((2, 4, n)) + 1j * rng.standard_normal((2, 4, n))
+    perm = rng.permutation(n)
+    np.testing.assert_array_equal(O.polconvert(A[..., perm], P[..., perm]), O.polconvert(A, P)[..., perm])
