@@ -44,6 +44,8 @@ WORKLOAD_TEXT = {
                       "sum w|V - degrid(G)|^2 and its gradients with respect to G and w (torch.autograd)",
     "mixed": "mixed precision: 512 antennas (130,816 baselines), 64 channels over 140-170 MHz, 8 time steps, "
              "4096x4096 complex64 grid per channel, Kaiser-Bessel W=16 OS=16, BF16x3 matrix-core grid and degrid",
+    "polconv": "polarisation conversion: 12 channels of 1125x1125-pixel images, four complex64 polarisation "
+               "products per pixel, one 4x4 complex64 matrix per pixel shared by the channels (162 MB)",
 }
 
 
@@ -75,24 +77,25 @@ def touched_cells(uvw_m, freq_hz, N, du, W, OS):
 
 
 KERNEL_SOURCES = ("tile_kernel.h", "tile_dispatch.h", "tile_fused.hip", "internal.h")
+POLCONV_SOURCES = ("polconv.hip", "internal.h")
 
 
-def kernel_source_sha():
-    """SHA-256 over the sources the fused tile kernel is compiled from."""
+def kernel_source_sha(names=KERNEL_SOURCES):
+    """SHA-256 over the sources a kernel is compiled from (default: the fused tile kernel)."""
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in names:
         h.update(open(os.path.join(ROOT, "paper_1003_5575_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused kernel from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "k_tile_fused_single_cadence_traffic.json")
+def measured_traffic(summary="k_tile_fused_single_cadence_traffic.json", names=KERNEL_SOURCES):
+    """HBM bytes per launch of a kernel from its committed counter summary, or None
+    when the kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         rec = json.load(open(path))
-        sha = kernel_source_sha()
+        sha = kernel_source_sha(names)
     except (OSError, ValueError):
         return None
     if rec.get("kernel_sources_sha256") != sha:
@@ -139,6 +142,8 @@ def main():
 
     if args.workload == "mixed":
         return bench_mixed(args, torch, rts, make_workload)
+    if args.workload == "polconv":
+        return bench_polconv(args, torch, rts)
     dev = torch.device("cuda:0")
     t0 = time.time()
     wl = make_workload(args.workload, seed=args.seed)
@@ -446,6 +451,70 @@ def bench_mixed(args, torch, rts, make_workload):
         "fp32_path": {"ms_per_step": round(ms32, 4), "value": round(n_valid / ms32 / 1e3, 1), "tile": tile32,
                       "plan_ms": round(p32, 4), "grid_ms": round(g32, 4), "degrid_ms": round(d32, 4)},
         "bf16x3_error": errs,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_polconv(args, torch, rts):
+    """Polarisation conversion S_i = A_i P_i on the image sizes of the paper's
+    timing run (12 channels, 1125 x 1125 pixels); a step is one rts_polconvert
+    launch over all channels.  HBM-bound: 128 bytes of matrix per pixel plus 64
+    bytes of products in and out per pixel and channel."""
+    from synth import make_polconv_inputs
+    n_side, C = 1125, 12
+    n = n_side * n_side
+    A_np, P_np = make_polconv_inputs(n, C, seed=args.seed)
+    A = torch.from_numpy(A_np).cuda()
+    P = torch.from_numpy(P_np).cuda()
+    S = torch.empty_like(P)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        rts.polconvert(A, P, out=S)
+    torch.cuda.synchronize()
+    K = args.steps
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(K):
+        rts.polconvert(A, P, out=S)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / K * 1e3
+    kms = float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(K)]))
+    alg = n * (16 * 8 + C * 8 * 8)
+    # reference: a 1 GiB device-to-device copy (read + write) on the same device
+    src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * (1 << 30) * 5 / e0.elapsed_time(e1) / 1e6
+    del src, dst
+    cpu = None
+    if not args.no_cpu:
+        from oracle import polconvert as opc
+        tc = time.perf_counter()
+        opc(A_np.reshape(4, 4, n), P_np)
+        dt = time.perf_counter() - tc
+        cpu = {"value": round(n * C / dt / 1e6, 2), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole workload ({C} channels x {n} pixels) in FP64 (numpy), {dt:.2f} s"}
+    out = {
+        "metric": "polarisation conversion S_i = A_i P_i, pixel-channels per second", "value":
+        round(n * C / ms / 1e3, 1), "unit": "Mpix/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["polconv"], "n_pix": n, "n_chan": C},
+        "roofline": {"bound": "hbm", "achieved": round(alg / kms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / kms / 1e6 / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("k_polconv_traffic.json", POLCONV_SOURCES),
+                     "kernel": "k_polconv_pairs" if n % 2 == 0 else "k_polconv_single", "kernel_ms": round(kms, 4),
+                     "alg_bytes_per_launch": alg, "device_copy_GBs": round(copy_gbs, 1)},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

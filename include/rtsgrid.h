@@ -192,7 +192,7 @@ rts_status rts_compute_coords(const rts_params *params, const double *uvw_m,
 rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream);
 
 /* Dirty image of every channel's grid (the imaging step after gridding,
- * Section 4): image[c] = shift(IFFT2(shift(grid[c]))) / (khat(nu_y) khat(nu_x)),
+ * Section 3, timed in Table 3): image[c] = shift(IFFT2(shift(grid[c]))) / (khat(nu_y) khat(nu_x)),
  * the centred inverse 2-D FFT without 1/N^2 normalisation, divided by the
  * separable grid correction, khat the Fourier transform of the plan's
  * Kaiser-Bessel window and nu = (q - N/2) / N for pixel q (pixel N/2 is l = 0).
@@ -203,6 +203,28 @@ rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream);
  * allocate nothing and are asynchronous on `stream`.
  * Errors: RTS_E_INVALID (NULL or misaligned), RTS_E_NOMEM, RTS_E_HIP. */
 rts_status rts_image(rts_plan_t plan, const float *grid, float *image_out, void *stream);
+
+/* Polarisation conversion (the polarisation convertor stage, Section 3; timed in
+ * Tables 3 and 4): for every pixel i of every channel c, S_i = A_i P_i, where P_i
+ * holds the pixel's four observed polarisation products and A_i is a 4x4 complex
+ * matrix supplied by a precomputation:
+ *     S[c][r][i] = sum_{k<4} A[r*4 + k][i] * P[c][k][i].
+ * Layouts (device memory, complex64 as interleaved float, caller-owned):
+ *   A  [16][n_pix]     entry r*4+k of every pixel's matrix, one plane per entry;
+ *                      channel c reads the planes starting a_chan_stride complex
+ *                      elements after A's start times c (a_chan_stride = 0: one
+ *                      set of matrices for all channels; else >= 16*n_pix)
+ *   P  [C][4][n_pix]   observed products, one plane per polarisation
+ *   S  [C][4][n_pix]   output; S may be the same buffer as P (in place), but must
+ *                      not overlap it otherwise, nor overlap A
+ * Pointers must be 8-byte aligned; with 16-byte alignment, an even n_pix and an
+ * even a_chan_stride, two pixels are converted per thread with 16-byte accesses.
+ * n_pix == 0 or n_chan == 0 is a no-op (pointers unchecked).  Asynchronous on
+ * `stream`; allocates nothing.
+ * Errors: RTS_E_INVALID (negative sizes, bad stride, NULL or misaligned
+ * pointers), RTS_E_HIP. */
+rts_status rts_polconvert(const float *A, const float *P, float *S, int64_t n_pix, int n_chan,
+                          int64_t a_chan_stride, void *stream);
 
 /* Copy the FP32 kernel table tab[p][j] = k(t_j - r_p/OS) (OS rows, W columns; rows
  * are phases r0..r0+OS-1, columns taps t0..t0+W-1 with r0 = -(OS/2), t0 = -(W-1)/2

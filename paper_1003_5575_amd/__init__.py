@@ -16,7 +16,7 @@ import ctypes
 from . import _lib
 from ._lib import RtsError, RtsParams, RtsPlanInfo  # noqa: F401
 
-__all__ = ["GridPlan", "CadenceGraph", "autotune_tile", "compute_coords", "RtsError", "library_path", "version", "GridFn", "DegridFn",
+__all__ = ["GridPlan", "CadenceGraph", "autotune_tile", "compute_coords", "polconvert", "RtsError", "library_path", "version", "GridFn", "DegridFn",
            "Chi2Fn", "grid", "degrid", "chi2"]
 
 
@@ -289,6 +289,31 @@ def autotune_tile(uvw, freq_hz, weights, vis, grid_in, n_grid, cell_lambda, supp
                                              ctypes.byref(best), ms if measure else None, tiles, 8,
                                              ctypes.byref(n)), "rts_autotune_tile")
     return best.value, {tiles[k]: ms[k] for k in range(n.value)}
+
+
+def polconvert(A, P, out=None, stream=None):
+    """Polarisation conversion S_i = A_i P_i per pixel (rts_polconvert).
+
+    A: complex64 [16, n_pix] (entry r*4+k of each pixel's 4x4 matrix, shared by
+    all channels) or [C, 16, n_pix] (one set per channel).  P: complex64
+    [C, 4, n_pix].  Returns S complex64 [C, 4, n_pix]; ``out`` may be P itself."""
+    torch = _torch()
+    if P.dim() != 3 or P.shape[1] != 4:
+        raise ValueError(f"P must have shape [C, 4, n_pix], got {tuple(P.shape)}")
+    C, n = int(P.shape[0]), int(P.shape[2])
+    _check_dev(P, "P", torch.complex64)
+    if A.dim() == 2:
+        _check_dev(A, "A", torch.complex64, (16, n))
+        stride = 0
+    else:
+        _check_dev(A, "A", torch.complex64, (C, 16, n))
+        stride = 16 * n
+    if out is None:
+        out = torch.empty_like(P)
+    _check_dev(out, "out", torch.complex64, (C, 4, n))
+    _lib.check(_lib.load().rts_polconvert(_ptr(A), _ptr(P), _ptr(out), n, C, stride, _stream(stream)),
+               "rts_polconvert")
+    return out
 
 
 def compute_coords(uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversample=8, stream=None):

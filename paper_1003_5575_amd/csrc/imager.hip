@@ -1,5 +1,5 @@
 // Imager: uv grid -> dirty image for every channel (the imaging step that
-// follows gridding in the paper's pipeline, Section 4).  The image is the
+// follows gridding in the paper's pipeline, Section 3).  The image is the
 // centred inverse 2-D FFT of the grid divided by the separable grid correction
 // khat(nu_x) khat(nu_y), nu = (q - N/2) / N, where khat is the Fourier transform
 // of the gridding kernel.  For even N the centring shifts are folded into sign

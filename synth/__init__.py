@@ -13,3 +13,4 @@ from .mwa import (  # noqa: F401
     make_workload,
     uvw_tracks,
 )
+from .polarisation import make_polconv_inputs  # noqa: F401

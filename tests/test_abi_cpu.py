@@ -103,3 +103,20 @@ def test_binding_refuses_cpu_tensors():
     import paper_1003_5575_amd as rts
     with pytest.raises(TypeError):
         rts.GridPlan(torch.zeros(4, 2, 3, dtype=torch.float64), [150e6], torch.zeros(1, 4, 2), 64, 10.0)
+
+
+def test_polconvert_argument_checks_on_host(lib):
+    """Host-side validation of rts_polconvert: no HIP call is reached."""
+    assert lib.rts_polconvert(None, None, None, -1, 1, 0, None) == 1
+    assert "n_pix and n_chan" in lib.rts_last_error().decode()
+    assert lib.rts_polconvert(None, None, None, 10, -2, 0, None) == 1
+    assert lib.rts_polconvert(None, None, None, 10, 1, 100, None) == 1     # stride below 16 * n_pix
+    assert "a_chan_stride" in lib.rts_last_error().decode()
+    assert lib.rts_polconvert(None, None, None, 1 << 40, 1, 0, None) == 1
+    assert "too large" in lib.rts_last_error().decode()
+    assert lib.rts_polconvert(None, None, None, 0, 4, 0, None) == 0         # empty: no-op
+    assert lib.rts_polconvert(None, None, None, 10, 0, 0, None) == 0
+    assert lib.rts_polconvert(None, None, None, 10, 2, 0, None) == 1
+    assert "non-NULL" in lib.rts_last_error().decode()
+    assert lib.rts_polconvert(ctypes.c_void_p(4), ctypes.c_void_p(8), ctypes.c_void_p(16), 10, 2, 0, None) == 1
+    assert "aligned" in lib.rts_last_error().decode()
