@@ -419,3 +419,58 @@ def test_polconvert_pixels_are_independent():
     P = rng.standard_normal((2, 4, n)) + 1j * rng.standard_normal((2, 4, n))
     perm = rng.permutation(n)
     np.testing.assert_array_equal(O.polconvert(A[..., perm], P[..., perm]), O.polconvert(A, P)[..., perm])
+
+
+# ------------------------------------------------ per-visibility (per-baseline) kernels
+def _small_pb(W, OS, conj=False, seed=0):
+    wl = make_workload("tiny", seed=seed)
+    freq = wl.freq_hz[wl.channels]
+    rng = np.random.default_rng(seed + 50)
+    w = rng.uniform(0.5, 1.5, wl.weights.shape)
+    geom = O.Geometry(wl.uvw_m, freq, w, 256, wl.cell_lambda, W, OS, conjugate=conj)
+    return wl, w, geom
+
+
+@pytest.mark.parametrize("W,OS,conj", [(7, 8, False), (24, 8, True), (8, 4, True)])
+def test_per_baseline_with_the_shared_table_is_plain_gridding(W, OS, conj):
+    """Every baseline given the Kaiser-Bessel table: identical to the pinned
+    shared-kernel gridding and degridding."""
+    wl, w, geom = _small_pb(W, OS, conj)
+    B = wl.uvw_m.shape[0]
+    tabs = np.broadcast_to(geom.tab, (B,) + geom.tab.shape)
+    np.testing.assert_array_equal(O.grid_per_baseline(geom, wl.vis, w, tabs), O.grid(geom, wl.vis, w))
+    G = np.random.default_rng(2).standard_normal((1, 256, 256)) + 0j
+    np.testing.assert_array_equal(O.degrid_per_baseline(geom, G, tabs), O.degrid(geom, G))
+
+
+@pytest.mark.parametrize("W,OS", [(7, 8), (24, 8)])
+def test_per_baseline_scaling_selects_each_baseline_and_phase(W, OS):
+    """Baseline b's table = s_b g[p] x (shared table row p): each sample's
+    contribution is scaled by s_b^2 g[r_y] g[r_x], i.e. shared-kernel gridding with
+    those factors folded into the weights.  A table taken from the wrong baseline
+    or the wrong phase row fails here."""
+    wl, w, geom = _small_pb(W, OS, seed=3)
+    B = wl.uvw_m.shape[0]
+    rng = np.random.default_rng(4)
+    s = rng.uniform(0.5, 2.0, B)
+    g = rng.uniform(0.5, 2.0, OS)
+    tabs = s[:, None, None] * (g[:, None] * geom.tab)[None]
+    cx, cy, rx, ry, valid = geom.copies[0]
+    r0 = geom.r[0]
+    w2 = w * (s[None, :, None] ** 2) * g[rx - r0] * g[ry - r0]
+    np.testing.assert_allclose(O.grid_per_baseline(geom, wl.vis, w, tabs), O.grid(geom, wl.vis, w2),
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_per_baseline_adjoint_identity():
+    """<grid(V), G> = <V, degrid(G)> with unit weights and random per-baseline tables."""
+    wl, _, geom = _small_pb(24, 8, seed=5)
+    B = wl.uvw_m.shape[0]
+    rng = np.random.default_rng(6)
+    tabs = rng.uniform(0.0, 1.0, (B, 8, 24))
+    ones = np.ones(wl.weights.shape)
+    geom1 = O.Geometry(wl.uvw_m, wl.freq_hz[wl.channels], ones, 256, wl.cell_lambda, 24, 8)
+    G = rng.standard_normal((1, 256, 256)) + 1j * rng.standard_normal((1, 256, 256))
+    lhs = np.vdot(O.grid_per_baseline(geom1, wl.vis, ones, tabs).ravel(), G.ravel())
+    rhs = np.vdot(np.asarray(wl.vis, np.complex128).ravel(), O.degrid_per_baseline(geom1, G, tabs).ravel())
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
