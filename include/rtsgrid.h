@@ -85,7 +85,8 @@ typedef enum {
 
 typedef struct {
   int32_t n_grid;       /* N: grid edge in cells, even, 16 <= N <= 8192                  */
-  int32_t support;      /* W: taps per axis, 2 <= W <= 16                                */
+  int32_t support;      /* W: taps per axis, 2 <= W <= 16 (BF16x3 plans: <= 24; beyond 16
+                           only rts_grid and rts_degrid are available)                   */
   int32_t oversample;   /* OS: kernel phases per cell, 1 <= OS <= 64                     */
   int32_t n_chan;       /* C >= 1                                                         */
   int32_t n_base;       /* B >= 1                                                         */
@@ -225,6 +226,24 @@ rts_status rts_image(rts_plan_t plan, const float *grid, float *image_out, void 
  * pointers), RTS_E_HIP. */
 rts_status rts_polconvert(const float *A, const float *P, float *S, int64_t n_pix, int n_chan,
                           int64_t a_chan_stride, void *stream);
+
+/* Per-visibility kernels (Section 3: the gridder's kernel is fixed by the
+ * calibration of the two tiles of each visibility's baseline; Table 4 uses a
+ * 24 x 24 kernel).  After this call rts_grid and rts_degrid of a BF16x3 plan use,
+ * for every sample of baseline b, the separable kernel of that baseline instead
+ * of the shared Kaiser-Bessel window:
+ *     grid[c][cy+t_v][cx+t_u] += w V tab[b][r_y][t_v] tab[b][r_x][t_u],
+ * with tab a device FP32 array [B][OS][W] in the phase / tap layout of
+ * rts_plan_get_table (same along u and v, the same for every channel; conjugate
+ * copies use their baseline's table at their own phases).  The values are copied
+ * into plan-owned padded tables (about 8*B*2*OS*(W+32) bytes, allocated on the
+ * first call); tab may be freed once the stream has passed this call.  A NULL tab
+ * frees them and restores the shared kernel.  rts_grid_degrid and cadence graphs
+ * keep the shared kernel and return RTS_E_UNSUPPORTED while per-baseline kernels
+ * are set.
+ * Errors: RTS_E_UNSUPPORTED (not a BF16x3 plan), RTS_E_INVALID, RTS_E_NOMEM,
+ * RTS_E_HIP. */
+rts_status rts_plan_set_baseline_kernels(rts_plan_t plan, const float *tab, void *stream);
 
 /* Copy the FP32 kernel table tab[p][j] = k(t_j - r_p/OS) (OS rows, W columns; rows
  * are phases r0..r0+OS-1, columns taps t0..t0+W-1 with r0 = -(OS/2), t0 = -(W-1)/2

@@ -166,6 +166,20 @@ class GridPlan:
         _lib.check(_lib.load().rts_degrid(self.handle, _ptr(grid), _ptr(out), _stream(stream)), "rts_degrid")
         return out
 
+    def set_baseline_kernels(self, tab, stream=None):
+        """Per-visibility kernels (rts_plan_set_baseline_kernels): ``tab`` float32
+        [B, OS, W] on the device, baseline b's separable kernel sampled in the
+        layout of ``table``; None restores the shared kernel.  BF16x3 plans only."""
+        torch = _torch()
+        if tab is None:
+            _lib.check(_lib.load().rts_plan_set_baseline_kernels(self.handle, None, _stream(stream)),
+                       "rts_plan_set_baseline_kernels")
+            return
+        p = self.params
+        _check_dev(tab, "tab", torch.float32, (p.n_base, p.oversample, p.support))
+        _lib.check(_lib.load().rts_plan_set_baseline_kernels(self.handle, _ptr(tab), _stream(stream)),
+                   "rts_plan_set_baseline_kernels")
+
     def image(self, grid, out=None, stream=None):
         """Dirty image of every channel: complex64 [C][N][N], the centred inverse FFT of
         the grid (unnormalised) divided by the grid correction (rts_image)."""

@@ -17,8 +17,8 @@ STATUS_NAMES = {0: "RTS_OK", 1: "RTS_E_INVALID", 2: "RTS_E_NOMEM", 3: "RTS_E_HIP
 EXPORTED = (
     "rts_grid_plan", "rts_plan_update", "rts_grid", "rts_degrid", "rts_grid_degrid", "rts_compute_coords",
     "rts_cadence_graph_create", "rts_cadence_graph_launch", "rts_cadence_graph_destroy", "rts_autotune_tile",
-    "rts_plan_valid_mask", "rts_image", "rts_polconvert", "rts_plan_get_table", "rts_plan_get_info", "rts_plan_destroy",
-    "rts_last_error", "rts_version",
+    "rts_plan_valid_mask", "rts_image", "rts_polconvert", "rts_plan_set_baseline_kernels", "rts_plan_get_table",
+    "rts_plan_get_info", "rts_plan_destroy", "rts_last_error", "rts_version",
 )
 
 
@@ -68,6 +68,7 @@ def load() -> ctypes.CDLL:
     lib.rts_compute_coords.argtypes = [ctypes.POINTER(RtsParams), P, P, P, P, P]
     lib.rts_plan_valid_mask.argtypes = [P, P, P]
     lib.rts_polconvert.argtypes = [P, P, P, I64, ctypes.c_int32, I64, P]
+    lib.rts_plan_set_baseline_kernels.argtypes = [P, P, P]
     lib.rts_cadence_graph_create.argtypes = [ctypes.POINTER(P), P, P, P, P, P, P, P, P, P]
     lib.rts_cadence_graph_launch.argtypes = [P, P]
     lib.rts_cadence_graph_destroy.argtypes = [P]
@@ -78,7 +79,8 @@ def load() -> ctypes.CDLL:
     for name in ("rts_cadence_graph_create", "rts_cadence_graph_launch", "rts_cadence_graph_destroy",
                  "rts_autotune_tile", "rts_grid_plan", "rts_plan_update", "rts_grid", "rts_degrid", "rts_grid_degrid", "rts_compute_coords",
                  "rts_cadence_graph_create", "rts_cadence_graph_launch", "rts_cadence_graph_destroy", "rts_autotune_tile",
-    "rts_plan_valid_mask", "rts_image", "rts_polconvert", "rts_plan_get_table", "rts_plan_get_info", "rts_plan_destroy"):
+    "rts_plan_valid_mask", "rts_image", "rts_polconvert", "rts_plan_set_baseline_kernels", "rts_plan_get_table",
+    "rts_plan_get_info", "rts_plan_destroy"):
         getattr(lib, name).restype = I
     lib.rts_last_error.restype = ctypes.c_char_p
     lib.rts_last_error.argtypes = []

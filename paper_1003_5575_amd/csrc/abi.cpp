@@ -83,8 +83,9 @@ rts_status validate(const rts_params *p) {
   RTS_REQUIRE(p != nullptr, "params is NULL");
   RTS_REQUIRE(p->n_grid >= 16 && p->n_grid <= kMaxN && p->n_grid % 2 == 0,
               "n_grid must be even and in [16, %d] (got %d)", kMaxN, p->n_grid);
-  RTS_REQUIRE(p->support >= 2 && p->support <= kMaxW, "support must be in [2, %d] (got %d)", kMaxW,
-              p->support);
+  const int wmax = p->precision == RTS_PREC_BF16X3 ? kMaxWMfma : kMaxW;
+  RTS_REQUIRE(p->support >= 2 && p->support <= wmax, "support must be in [2, %d] for this precision (got %d)",
+              wmax, p->support);
   RTS_REQUIRE(p->oversample >= 1 && p->oversample <= kMaxOS, "oversample must be in [1, %d] (got %d)",
               kMaxOS, p->oversample);
   RTS_REQUIRE(p->n_chan >= 1 && p->n_base >= 1 && p->n_time >= 1,
@@ -165,6 +166,8 @@ void free_plan(Plan *P) {
   hipFree(P->d_tabE);
   hipFree(P->d_tab_hi);
   hipFree(P->d_tab_lo);
+  hipFree(P->d_pb_thl);
+  hipFree(P->d_pb_tab);
   hipFree(P->d_scale);
   hipFree(P->d_coords);
   hipFree(P->d_list);
@@ -382,15 +385,21 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   P->nkeys = (int64_t)P->C * P->nT2;
   RTS_REQUIRE(P->nkeys < ((int64_t)1 << 31), "too many (channel, tile) pairs");
   P->seg_max = choose_seg_max(P->W, P->T);
-  if (!tile_supported(P->W, P->seg_max)) {
+  // supports beyond the FP32 tile kernels' range run on the matrix-core path only
+  if (P->W <= kMaxW && !tile_supported(P->W, P->seg_max)) {
     set_error("support %d is not instantiated", P->W);
+    return RTS_E_UNSUPPORTED;
+  }
+  if (P->precision == RTS_PREC_BF16X3 && mfma_lds_bytes(P->WN, 2 * P->OS, P->tile) > 65536) {
+    set_error("support %d, oversample %d and tile %d need more than 64 KiB of LDS on the matrix-core path",
+              P->W, P->OS, P->tile);
     return RTS_E_UNSUPPORTED;
   }
   fill_tables(*P);
   RTS_HIP(hipGetDevice(&P->device));
   RTS_HIP(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device));
   P->schedule = params->schedule == RTS_SCHEDULE_AUTO ? RTS_SCHEDULE_TILES : params->schedule;
-  RTS_HIP(prepare_tile_kernels(*P));
+  if (P->W <= kMaxW) RTS_HIP(prepare_tile_kernels(*P));
   hipStream_t s = (hipStream_t)stream;
 
   const int64_t nsamp = (int64_t)P->C * P->B * P->T;
@@ -524,6 +533,10 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
     set_error("rts_grid_degrid does not support plans built with conjugate=1");
     return RTS_E_UNSUPPORTED;
   }
+  if (plan->W > kMaxW || plan->d_pb_thl) {
+    set_error("the fused step runs the FP32 tile kernels: support <= %d and the shared kernel only", kMaxW);
+    return RTS_E_UNSUPPORTED;
+  }
   RTS_REQUIRE(vis && weights && grid_in && grid_out, "vis, weights, grid_in, grid_out must be non-NULL");
   RTS_REQUIRE(aligned(vis, 8) && aligned(weights, 4) && aligned(grid_in, 8) && aligned(grid_out, 16) &&
                   aligned(model_out, 8) && aligned(chi2_out, 8),
@@ -570,6 +583,35 @@ rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream) {
   RTS_REQUIRE(mask != nullptr, "mask is NULL");
   const int64_t n = (int64_t)plan->C * plan->B * plan->T;
   RTS_HIP(launch_valid_mask(plan->d_coords, mask, plan->B, plan->T, plan->ncopy, n, (hipStream_t)stream));
+  return RTS_OK;
+}
+
+rts_status rts_plan_set_baseline_kernels(rts_plan_t plan, const float *tab, void *stream) {
+  if (rts_status st = check_plan(plan)) return st;
+  if (plan->precision != RTS_PREC_BF16X3) {
+    set_error("per-baseline kernels need a BF16x3 plan");
+    return RTS_E_UNSUPPORTED;
+  }
+  if (!tab) {
+    hipFree(plan->d_pb_thl);
+    hipFree(plan->d_pb_tab);
+    plan->d_pb_thl = nullptr;
+    plan->d_pb_tab = nullptr;
+    return RTS_OK;
+  }
+  RTS_REQUIRE(aligned(tab, 4), "tab must be 4-byte aligned");
+  if (!plan->d_pb_thl) {
+    const size_t words = (size_t)pb_table_words(*plan);
+    RTS_HIP(dalloc(&plan->d_pb_thl, words));
+    hipError_t e = dalloc(&plan->d_pb_tab, words);
+    if (e != hipSuccess) {
+      hipFree(plan->d_pb_thl);
+      plan->d_pb_thl = nullptr;
+      set_error("device allocation of %zu bytes failed", 8 * words);
+      return RTS_E_NOMEM;
+    }
+  }
+  RTS_HIP(build_baseline_tables(*plan, tab, (hipStream_t)stream));
   return RTS_OK;
 }
 

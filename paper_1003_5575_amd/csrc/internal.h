@@ -13,6 +13,7 @@
 namespace rts {
 
 constexpr int kMaxW = 16;
+constexpr int kMaxWMfma = 24;   // supports up to this on the matrix-core path (BF16x3 plans)
 constexpr int kMaxOS = 64;
 constexpr int kMaxN = 8192;
 constexpr int kMaxTile = 64;     // FP64 tile accumulator: 16*64*64 B = 64 KiB of LDS
@@ -123,6 +124,8 @@ struct rts_plan_s {
   float *d_tabE = nullptr;
   uint16_t *d_tab_hi = nullptr;
   uint16_t *d_tab_lo = nullptr;
+  uint32_t *d_pb_thl = nullptr;   // per-baseline padded kernel rows (packed hi|lo), NULL = shared kernel
+  float *d_pb_tab = nullptr;      // per-baseline padded kernel rows (FP32)
   double *d_scale = nullptr;
   uint16_t *d_coords = nullptr;
   uint2 *d_list = nullptr;
@@ -165,6 +168,11 @@ hipError_t launch_chi2_reduce(const double *part, int64_t n, double *out, hipStr
 hipError_t launch_valid_mask(const uint16_t *coords, uint8_t *mask, int B, int T, int ncopy, int64_t n,
                              hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+// Matrix-core path: largest LDS need of its kernels for this geometry (bytes),
+// per-baseline table size (words per table) and its construction.
+size_t mfma_lds_bytes(int WN, int OS2, int tile);
+int64_t pb_table_words(const Plan &P);
+hipError_t build_baseline_tables(const Plan &P, const float *tab, hipStream_t s);
 
 // tile kernels (tile_*.hip)
 template <int MODE>

@@ -23,6 +23,10 @@
 // empty slot points at the leading zeros.  Building the MFMA operands is then
 // reads, packing and (for gridding) the split of w V times the column weight.
 //
+// With a kernel per baseline (rts_plan_set_baseline_kernels) the same padded
+// rows are built per baseline in device memory (every region edge padded to 32)
+// and read from there; the slot then holds word offsets into those tables.
+//
 // Gridding accumulators stay in registers (no atomics); degridding reduces each
 // sample's partial value over the region columns with DPP and adds it to the
 // (zeroed) model with FP32 atomics, one atomic instruction per chunk.
@@ -63,6 +67,17 @@ __host__ __device__ __forceinline__ PadGeom pad_geom(int WN, int OS2, int RH, in
   p.TA = RH + OS2 * p.SA;
   return p;
 }
+
+// Per-baseline padded tables in device memory: for baseline b, FP32 weights at
+// tab[b*TX + 32 + s*SX + i] and packed hi|lo words at thl[b*TA + 32 + s*SA + i]
+// (extended row s, window column i), zero elsewhere; both strides WN + 31, so
+// any region edge up to 32 reads zeros off the support.
+struct PbTables {
+  uint32_t *thl;
+  float *tab;
+  int TA, TX, SA, SX;
+};
+constexpr int kPbPad = 32;
 
 // Two products a0*k0, a1*k1 split into packed BF16 pairs: hi = bf16(p) (round to
 // nearest even), lo = bf16(p - hi) with the residual taken by an FMA.
@@ -174,21 +189,33 @@ __device__ __forceinline__ void slot_addresses(const TileArgs &a, const PadGeom 
   xa = 4u * (uint32_t)(RW + sx * pg.SX - dx);
 }
 
+// Word offsets of a sample's per-baseline table entries for region row and
+// column 0 (the per-baseline form of slot_addresses); vi is the visibility index
+// (c*B + b)*T + t.
+__device__ __forceinline__ void slot_offsets_pb(const TileArgs &a, const PbTables &pb, uint32_t vi, uint32_t recy,
+                                                uint16_t cw, int x0, int y0, uint32_t &ya, uint32_t &xa) {
+  const int dx = (int)(recy & kRecXMask) - x0;
+  const int dy = (int)((recy >> kRecYShift) & kRecXMask) - y0;
+  const int sx = cw & 0x7F, sy = (cw >> 7) & 0x7F;
+  const uint32_t bl = (vi / (uint32_t)a.T) % (uint32_t)a.B;
+  ya = bl * (uint32_t)pb.TA + (uint32_t)(kPbPad + sy * pb.SA - dy);
+  xa = bl * (uint32_t)pb.TX + (uint32_t)(kPbPad + sx * pb.SX - dx);
+}
+
 // Gridding of a region of GR x 1 subtiles (16 GR rows, 16 columns): the B
 // operand (w V times the column weights, the costlier one to build) is shared
 // by the GR row blocks.  One v_mfma_f32_16x16x32_bf16 per term and block: K
 // runs over 32 sample slots.  Registers are capped at 80 so that three
 // workgroups of 8 waves share a CU.
-template <int GR>
+template <int GR, bool PB>
 __global__ __launch_bounds__(64 * max_waves<GR>()) __attribute__((amdgpu_waves_per_eu(6)))
-void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
-                                                                           const uint16_t *tab_lo) {
+void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_lo, PbTables pb) {
   constexpr int kChunk = 32;                         // sample slots per MFMA K step
   constexpr int RH = GR * kMT, RW = kMT;
   __shared__ uint4 slots[max_waves<GR>()][kChunk];
   __shared__ uint2 queue[max_waves<GR>()][kQueue];
   const PadGeom pg = pad_geom(a.WN, a.OS2, RH, RW);
-  const char *lds = load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
+  const char *lds = PB ? nullptr : load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int nwx = a.tile / RW;                      // regions per tile row
@@ -200,7 +227,7 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
   const uint32_t cap = (uint32_t)a.list_cap;
   const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
   const size_t copy_stride = (size_t)a.B * a.T;
-  const uint32_t empty_ya = 4u * (uint32_t)pg.TX, empty_xa = 0u;
+  const uint32_t empty_ya = PB ? 0u : 4u * (uint32_t)pg.TX, empty_xa = 0u;
 
   f4_t acc_re[GR], acc_im[GR];
 #pragma unroll
@@ -231,7 +258,10 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
           const float2 v = a.vis[vi];
           const float wt = a.w[vi];
           uint32_t ya, xa;
-          slot_addresses(a, pg, RH, RW, rec.y, cw, x0, y0, ya, xa);
+          if (PB)
+            slot_offsets_pb(a, pb, (uint32_t)vi, rec.y, cw, x0, y0, ya, xa);
+          else
+            slot_addresses(a, pg, RH, RW, rec.y, cw, x0, y0, ya, xa);
           const bool ok = (cw & kCoordValid) != 0;
           sl.x = ok ? ya : empty_ya;
           sl.y = ok ? xa : empty_xa;
@@ -254,10 +284,17 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const uint4 sl = ss[8 * g + 2 * p + h];
-        const uint32_t ya = sl.x + 4u * i16, xa = sl.y + 4u * i16;
+        if (PB) {
+          const uint32_t ya = sl.x + i16, xa = sl.y + i16;
 #pragma unroll
-        for (int rb = 0; rb < GR; ++rb) av[rb][h] = lds_u32(lds, ya + 4u * kMT * rb);
-        kx[h] = lds_f32(lds, xa);
+          for (int rb = 0; rb < GR; ++rb) av[rb][h] = pb.thl[ya + kMT * rb];
+          kx[h] = pb.tab[xa];
+        } else {
+          const uint32_t ya = sl.x + 4u * i16, xa = sl.y + 4u * i16;
+#pragma unroll
+          for (int rb = 0; rb < GR; ++rb) av[rb][h] = lds_u32(lds, ya + 4u * kMT * rb);
+          kx[h] = lds_f32(lds, xa);
+        }
         ar[h] = __uint_as_float(sl.z);
         ai[h] = __uint_as_float(sl.w);
       }
@@ -324,15 +361,15 @@ __device__ __forceinline__ float dpp_xor1(float v) {
 // model value over the region is sum_x H[s][x] k_x(x).  A window crossing
 // region edges is covered by every region it touches, so the partial values are
 // added to the (zeroed) model with FP32 atomics.
-template <int DC>
+template <int DC, bool PB>
 __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
-                                                                             const uint16_t *tab_lo) {
+                                                                             const uint16_t *tab_lo, PbTables pb) {
   constexpr int kChunk = 16;
   constexpr int RH = kMT, RW = DC * kMT;
   __shared__ uint4 dslots[max_waves<DC>()][kChunk];
   __shared__ uint2 queue[max_waves<DC>()][kQueue];
   const PadGeom pg = pad_geom(a.WN, a.OS2, RH, RW);
-  const char *lds = load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
+  const char *lds = PB ? nullptr : load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nwx = a.tile / RW;                      // regions per tile row
@@ -344,7 +381,7 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
   const uint32_t cap = (uint32_t)a.list_cap;
   const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
   const int i16 = lane & 15, g = lane >> 4;
-  const uint32_t empty_ya = 4u * (uint32_t)pg.TX, empty_xa = 0u;
+  const uint32_t empty_ya = PB ? 0u : 4u * (uint32_t)pg.TX, empty_xa = 0u;
 
   // B operands, loaded once: lane (x = i16, g) of block cb holds rows 4g + e of
   // Re G and Im G at region column 16 cb + x, split into hi and lo parts.
@@ -382,7 +419,10 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
           const size_t vi = rec.x + j;
           const uint16_t cw = a.coords[vi + (size_t)(c * (a.ncopy - 1)) * ((size_t)a.B * a.T)];
           uint32_t ya, xa;
-          slot_addresses(a, pg, RH, RW, rec.y, cw, x0, y0, ya, xa);
+          if (PB)
+            slot_offsets_pb(a, pb, (uint32_t)vi, rec.y, cw, x0, y0, ya, xa);
+          else
+            slot_addresses(a, pg, RH, RW, rec.y, cw, x0, y0, ya, xa);
           const bool ok = (cw & kCoordValid) != 0;
           sl.x = ok ? ya : empty_ya;
           sl.y = ok ? xa : empty_xa;
@@ -397,9 +437,20 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     // A operand: lane (s = i16, g) holds k_y of sample s at region rows 4g + e.
     s4_t ah, al;
     {
-      const uint32_t ya = ds[i16].x + 16u * g;
-      const uint32_t t0 = lds_u32(lds, ya), t1 = lds_u32(lds, ya + 4u);
-      const uint32_t t2 = lds_u32(lds, ya + 8u), t3 = lds_u32(lds, ya + 12u);
+      uint32_t t0, t1, t2, t3;
+      if (PB) {
+        const uint32_t ya = ds[i16].x + 4u * g;
+        t0 = pb.thl[ya];
+        t1 = pb.thl[ya + 1];
+        t2 = pb.thl[ya + 2];
+        t3 = pb.thl[ya + 3];
+      } else {
+        const uint32_t ya = ds[i16].x + 16u * g;
+        t0 = lds_u32(lds, ya);
+        t1 = lds_u32(lds, ya + 4u);
+        t2 = lds_u32(lds, ya + 8u);
+        t3 = lds_u32(lds, ya + 12u);
+      }
       ah = __builtin_bit_cast(s4_t, u2_t{lows(t0, t1), lows(t2, t3)});
       al = __builtin_bit_cast(s4_t, u2_t{highs(t0, t1), highs(t2, t3)});
     }
@@ -425,11 +476,10 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const uint4 sl = ds[4 * g + r];
-      const uint32_t xa = sl.y + 4u * i16;
       v[2 * r] = v[2 * r + 1] = 0.0f;
 #pragma unroll
       for (int cb = 0; cb < DC; ++cb) {
-        const float kx = lds_f32(lds, xa + 4u * kMT * cb);
+        const float kx = PB ? pb.tab[sl.y + i16 + kMT * cb] : lds_f32(lds, sl.y + 4u * i16 + 4u * kMT * cb);
         v[2 * r] += hr[cb][r] * kx;
         v[2 * r + 1] += hi[cb][r] * kx;
       }
@@ -460,19 +510,80 @@ size_t padded_lds_bytes(const TileArgs &a, int RH, int RW) {
   return (size_t)16 * (size_t)((pg.TX + pg.TA + 3) / 4);
 }
 
+PbTables pb_tables(const Plan &P) {
+  PbTables pb{};
+  pb.thl = P.d_pb_thl;
+  pb.tab = P.d_pb_tab;
+  pb.SA = pb.SX = P.WN + kPbPad - 1;
+  pb.TA = pb.TX = kPbPad + 2 * P.OS * pb.SA;
+  return pb;
+}
+
+// Per-baseline padded rows from the caller's [B][OS][W] table (layout above).
+__global__ void k_build_pb_tables(const float *__restrict__ tab, int64_t total, int OS, int W, int WN, PbTables pb) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= total) return;
+  const int per = 2 * OS * WN;
+  const int64_t b = idx / per;
+  const int rem = (int)(idx - b * per);
+  const int srow = rem / WN, i = rem - srow * WN;
+  const int d = srow / OS, p = srow - d * OS, j = i - d;
+  const float v = (j >= 0 && j < W) ? tab[(b * OS + p) * W + j] : 0.0f;
+  pb.tab[b * pb.TX + kPbPad + srow * pb.SX + i] = v;
+  const __bf16 h = (__bf16)v;
+  const __bf16 l = (__bf16)(v - (float)h);
+  const uint32_t w = (uint32_t)__builtin_bit_cast(uint16_t, h) | ((uint32_t)__builtin_bit_cast(uint16_t, l) << 16);
+  pb.thl[b * pb.TA + kPbPad + srow * pb.SA + i] = w;
+}
+
 }  // namespace
+
+size_t mfma_lds_bytes(int WN, int OS2, int tile) {
+  const int pair = tile % (2 * kMT) == 0 ? 2 : 1;
+  const size_t waves = (size_t)max_waves<1>();
+  const size_t grid_static = pair == 2 ? (size_t)max_waves<2>() * (32 * 16 + kQueue * 8) : waves * (32 * 16 + kQueue * 8);
+  const size_t degrid_static = pair == 2 ? (size_t)max_waves<2>() * (16 * 16 + kQueue * 8) : waves * (16 * 16 + kQueue * 8);
+  const PadGeom g = pad_geom(WN, OS2, pair * kMT, kMT), d = pad_geom(WN, OS2, kMT, pair * kMT);
+  const size_t gl = grid_static + (size_t)16 * ((g.TX + g.TA + 3) / 4);
+  const size_t dl = degrid_static + (size_t)16 * ((d.TX + d.TA + 3) / 4);
+  return std::max(gl, dl);
+}
+
+int64_t pb_table_words(const Plan &P) {
+  return (int64_t)P.B * (kPbPad + 2 * P.OS * (P.WN + kPbPad - 1));
+}
+
+hipError_t build_baseline_tables(const Plan &P, const float *tab, hipStream_t s) {
+  const PbTables pb = pb_tables(P);
+  const int64_t words = pb_table_words(P);
+  hipError_t e = launch_fill_u32(P.d_pb_thl, words, 0u, s);
+  if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(P.d_pb_tab), words, 0u, s);
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)P.B * 2 * P.OS * P.WN;
+  hipLaunchKernelGGL(k_build_pb_tables, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, tab, total, P.OS,
+                     P.W, P.WN, pb);
+  return hipGetLastError();
+}
 
 // Regions of two subtiles per wave where the tile edge is a multiple of 32.
 hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   const int pair = P.tile % (2 * kMT) == 0 ? 2 : 1;
   const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT) / pair);
-  const size_t lds = padded_lds_bytes(a, pair * kMT, kMT);
-  if (pair == 2)
-    hipLaunchKernelGGL(k_grid_mfma_bf16x3<2>, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
-                       P.d_tab_lo);
-  else
-    hipLaunchKernelGGL(k_grid_mfma_bf16x3<1>, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
-                       P.d_tab_lo);
+  const bool pbk = P.d_pb_thl != nullptr;
+  const size_t lds = pbk ? 0 : padded_lds_bytes(a, pair * kMT, kMT);
+  const PbTables pb = pb_tables(P);
+  const dim3 grid((unsigned)P.nkeys), block(threads);
+  if (pair == 2) {
+    if (pbk)
+      hipLaunchKernelGGL((k_grid_mfma_bf16x3<2, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
+    else
+      hipLaunchKernelGGL((k_grid_mfma_bf16x3<2, false>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
+  } else {
+    if (pbk)
+      hipLaunchKernelGGL((k_grid_mfma_bf16x3<1, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
+    else
+      hipLaunchKernelGGL((k_grid_mfma_bf16x3<1, false>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
+  }
   return hipGetLastError();
 }
 
@@ -482,13 +593,21 @@ hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int pair = P.tile % (2 * kMT) == 0 ? 2 : 1;
   const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT) / pair);
-  const size_t lds = padded_lds_bytes(a, kMT, pair * kMT);
-  if (pair == 2)
-    hipLaunchKernelGGL(k_degrid_mfma_bf16x3<2>, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
-                       P.d_tab_lo);
-  else
-    hipLaunchKernelGGL(k_degrid_mfma_bf16x3<1>, dim3((unsigned)P.nkeys), dim3(threads), lds, s, a, P.d_tab_hi,
-                       P.d_tab_lo);
+  const bool pbk = P.d_pb_thl != nullptr;
+  const size_t lds = pbk ? 0 : padded_lds_bytes(a, kMT, pair * kMT);
+  const PbTables pb = pb_tables(P);
+  const dim3 grid((unsigned)P.nkeys), block(threads);
+  if (pair == 2) {
+    if (pbk)
+      hipLaunchKernelGGL((k_degrid_mfma_bf16x3<2, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
+    else
+      hipLaunchKernelGGL((k_degrid_mfma_bf16x3<2, false>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
+  } else {
+    if (pbk)
+      hipLaunchKernelGGL((k_degrid_mfma_bf16x3<1, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
+    else
+      hipLaunchKernelGGL((k_degrid_mfma_bf16x3<1, false>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
+  }
   return hipGetLastError();
 }
 

@@ -49,6 +49,10 @@ rts_status rts_cadence_graph_create(rts_graph_t *out, rts_plan_t plan, const dou
     set_error("cadence graphs need a plan without conjugate copies");
     return RTS_E_UNSUPPORTED;
   }
+  if (plan->W > kMaxW || plan->d_pb_thl) {
+    set_error("cadence graphs run the FP32 fused step: support <= %d and the shared kernel only", kMaxW);
+    return RTS_E_UNSUPPORTED;
+  }
   hipStream_t cs = nullptr;
   RTS_HIP_R(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   // the captured work must follow whatever the caller already queued

@@ -14,3 +14,4 @@ from .mwa import (  # noqa: F401
     uvw_tracks,
 )
 from .polarisation import make_polconv_inputs  # noqa: F401
+from .gcf import make_baseline_kernels  # noqa: F401
