@@ -114,6 +114,9 @@ CONFIGS = {
                              weights="uniform"),
     # 64 channels, 8 steps, 4096^2, W=16, OS=16
     "mixed": Config("mixed", 512, 8, 64, 140e6, 30e6 / 64, 4096, 16, 16, n_sources=10),
+    # per-visibility kernels at the paper's timing-run sizes (12 channels, a 24 x 24
+    # kernel, ~1125^2 images: 1152^2 is the nearest grid edge divisible by 64), 8 steps
+    "pervis": Config("pervis", 512, 8, 12, 140e6, 30e6 / 12, 1152, 24, 8, n_sources=10),
 }
 
 
