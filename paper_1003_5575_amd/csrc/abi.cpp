@@ -420,7 +420,13 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
     RTS_HIP(dalloc(&P->d_hist, (size_t)nhist));
     RTS_HIP(dalloc(&P->d_desc, (size_t)P->C * P->ncopy * P->B));
   }
-  if (P->schedule == RTS_SCHEDULE_PERSISTENT) {
+  // Longest-first order: for the persistent launch, and for the matrix-core
+  // kernels when there are few tiles per resident workgroup (at most 64 per CU,
+  // about 20 per workgroup slot), where a few dense tiles otherwise run last;
+  // with more tiles the tail is short and the ordering pass costs more than it
+  // saves.
+  const bool mfma_order = P->precision == RTS_PREC_BF16X3 && P->nkeys <= (int64_t)64 * P->n_cu;
+  if (P->schedule == RTS_SCHEDULE_PERSISTENT || mfma_order) {
     RTS_HIP(dalloc(&P->d_order, (size_t)P->nkeys));
     RTS_HIP(dalloc(&P->d_lpt, (size_t)kLptWords));
   }

@@ -90,7 +90,7 @@ struct TileArgs {
   int write_model;
   int vec;                   // whole-track segments may use 16-byte vector loads and stores
   int seg_max;               // most samples per segment (a power of two)
-  const uint32_t *order;     // persistent launch: tiles in per-XCD longest-first order
+  const uint32_t *order;     // tiles in per-XCD longest-first order (persistent launch, matrix-core kernels)
   uint32_t *queue;           // persistent launch: 8 queue counters (zeroed before launch)
 };
 
@@ -184,8 +184,9 @@ double bessel_i0(double x);
 void destroy_imager(Plan *P);
 hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s);
 hipError_t launch_lpt_order(const uint32_t *tile_off, int64_t nkeys, uint32_t *lpt, uint32_t *order, hipStream_t s);
-// Longest-first tile order for the persistent launch: tiles are bucketed by their
-// work-list length (clamped to kLptBins-1) within each eighth of the tile range.
+// Longest-first tile order (persistent launch, matrix-core kernels): tiles are
+// bucketed by their work-list length (16 buckets per octave) within each eighth
+// of the tile range.
 // Workspace layout (uint32 words): bucket counts, then their exclusive scan
 // (8*kLptBins+1 words), scan block sums, and the eight queue counters.
 constexpr int kLptBins = 1024;

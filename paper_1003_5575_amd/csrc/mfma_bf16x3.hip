@@ -176,6 +176,20 @@ __device__ __forceinline__ void for_subtile_chunks(const TileArgs &a, uint32_t b
   if (qn > 0) chunk(qn);
 }
 
+// The (channel, tile) key of this workgroup, or -1 for a workgroup with none.
+// With a longest-first order (a.order), workgroup b takes position b / 8 of
+// eighth b mod 8 of the tile range: each XCD (workgroups go to the eight XCDs in
+// turn) walks one contiguous eighth, its heaviest tiles first, which shortens
+// the tail where a few dense uv tiles would otherwise run last.  Without it,
+// xcd_remap gives each XCD its eighth in key order.
+__device__ __forceinline__ int tile_key(const TileArgs &a) {
+  if (!a.order) return xcd_remap(blockIdx.x, gridDim.x);
+  const int per = (a.nkeys + 7) / 8;
+  const int g = blockIdx.x & 7, i = blockIdx.x >> 3;
+  if (i >= min(per, a.nkeys - g * per)) return -1;
+  return (int)a.order[g * per + i];
+}
+
 // LDS byte addresses of a sample's table entries for region row 0 (packed hi|lo
 // row weights) and region column 0 (FP32 column weights).  The queue filter
 // keeps dy in [-(WN-1), RH-1] and dx in [-(WN-1), RW-1], so every read at
@@ -214,12 +228,13 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
   constexpr int RH = GR * kMT, RW = kMT;
   __shared__ uint4 slots[max_waves<GR>()][kChunk];
   __shared__ uint2 queue[max_waves<GR>()][kQueue];
+  const int key = tile_key(a);
+  if (key < 0) return;
   const PadGeom pg = pad_geom(a.WN, a.OS2, RH, RW);
   const char *lds = PB ? nullptr : load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int nwx = a.tile / RW;                      // regions per tile row
-  const int key = xcd_remap(blockIdx.x, gridDim.x);
   const int c = key / a.nT2;
   const int rem = key - c * a.nT2;
   const int ty = rem / a.nT, tx = rem - ty * a.nT;
@@ -368,12 +383,13 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
   constexpr int RH = kMT, RW = DC * kMT;
   __shared__ uint4 dslots[max_waves<DC>()][kChunk];
   __shared__ uint2 queue[max_waves<DC>()][kQueue];
+  const int key = tile_key(a);
+  if (key < 0) return;
   const PadGeom pg = pad_geom(a.WN, a.OS2, RH, RW);
   const char *lds = PB ? nullptr : load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nwx = a.tile / RW;                      // regions per tile row
-  const int key = xcd_remap(blockIdx.x, gridDim.x);
   const int c = key / a.nT2;
   const int rem = key - c * a.nT2;
   const int ty = rem / a.nT, tx = rem - ty * a.nT;
@@ -565,6 +581,12 @@ hipError_t build_baseline_tables(const Plan &P, const float *tab, hipStream_t s)
   return hipGetLastError();
 }
 
+// Workgroups to launch: one per key, or 8 * ceil(nkeys / 8) with the
+// longest-first order (see tile_key).
+static unsigned mfma_grid_size(const Plan &P, const TileArgs &a) {
+  return a.order ? (unsigned)(8 * ((P.nkeys + 7) / 8)) : (unsigned)P.nkeys;
+}
+
 // Regions of two subtiles per wave where the tile edge is a multiple of 32.
 hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   const int pair = P.tile % (2 * kMT) == 0 ? 2 : 1;
@@ -572,7 +594,7 @@ hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   const bool pbk = P.d_pb_thl != nullptr;
   const size_t lds = pbk ? 0 : padded_lds_bytes(a, pair * kMT, kMT);
   const PbTables pb = pb_tables(P);
-  const dim3 grid((unsigned)P.nkeys), block(threads);
+  const dim3 grid(mfma_grid_size(P, a)), block(threads);
   if (pair == 2) {
     if (pbk)
       hipLaunchKernelGGL((k_grid_mfma_bf16x3<2, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
@@ -596,7 +618,7 @@ hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   const bool pbk = P.d_pb_thl != nullptr;
   const size_t lds = pbk ? 0 : padded_lds_bytes(a, kMT, pair * kMT);
   const PbTables pb = pb_tables(P);
-  const dim3 grid((unsigned)P.nkeys), block(threads);
+  const dim3 grid(mfma_grid_size(P, a)), block(threads);
   if (pair == 2) {
     if (pbk)
       hipLaunchKernelGGL((k_degrid_mfma_bf16x3<2, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);

@@ -782,12 +782,20 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
 // Longest-first tile order per XCD range (persistent launch): tiles are bucketed by
 // their work-list length (clamped to kLptBins-1), longest bucket first, within the
 // eighth of the tile range each XCD owns.
+// Bucket of a tile with n listings, heaviest first: an increasing map of n with
+// 16 buckets per octave (exponent and the next four bits of n + 1), reversed.
+__device__ __forceinline__ int lpt_bin(uint32_t n) {
+  const uint32_t m = n + 1u;
+  const int e = 31 - __clz((int)m);
+  const int f = e >= 4 ? (int)((m >> (e - 4)) & 15u) : (int)((m << (4 - e)) & 15u);
+  return kLptBins - 1 - min(e * 16 + f, kLptBins - 1);
+}
+
 __global__ __launch_bounds__(kBlock) void k_lpt_count(const uint32_t *tile_off, int64_t nkeys, uint32_t *cnt) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nkeys) return;
   const int64_t per = (nkeys + 7) / 8;
-  const uint32_t n = tile_off[k + 1] - tile_off[k];
-  const int bin = kLptBins - 1 - (int)min(n, (uint32_t)(kLptBins - 1));
+  const int bin = lpt_bin(tile_off[k + 1] - tile_off[k]);
   atomicAdd(&cnt[(k / per) * kLptBins + bin], 1u);
 }
 
@@ -796,8 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_lpt_scatter(const uint32_t *tile_off
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nkeys) return;
   const int64_t per = (nkeys + 7) / 8;
-  const uint32_t n = tile_off[k + 1] - tile_off[k];
-  const int bin = kLptBins - 1 - (int)min(n, (uint32_t)(kLptBins - 1));
+  const int bin = lpt_bin(tile_off[k + 1] - tile_off[k]);
   const uint32_t pos = atomicAdd(&cursor[(k / per) * kLptBins + bin], 1u);
   order[pos] = (uint32_t)k;
 }

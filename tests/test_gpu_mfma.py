@@ -118,3 +118,24 @@ def test_bf16x3_degrid_is_adjoint_of_bf16x3_grid(rts):
     lhs = np.vdot(G.ravel(), Gin.astype(np.complex128).ravel())
     rhs = np.vdot(wl.vis.astype(np.complex128).ravel(), M.ravel())
     assert abs(lhs - rhs) <= 1e-4 * max(abs(lhs), 1.0)
+
+
+def test_bf16x3_in_key_order_with_many_tiles(rts):
+    """More (channel, tile) pairs than 64 per CU: the kernels walk the tiles in
+    key order instead of longest first (the small cases above take the
+    longest-first order); both grid and degrid against the oracle."""
+    N, W, OS = 2048, 7, 8
+    wl, freq, du = small_case(n_ant=40, channels=(2, 30), N=N, W=W, OS=OS, flag_frac=0.1)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, tile=16, precision="bf16x3")
+    assert 2 * (N // 16) ** 2 > 64 * torch.cuda.get_device_properties(0).multi_processor_count
+    geom = O.Geometry(wl.uvw_m, freq, wl.weights, N, du, W, OS)
+    G = plan.grid(vis, w).cpu().numpy()
+    Gref = O.grid(geom, wl.vis, wl.weights)
+    rng = np.random.default_rng(5)
+    Gin = (rng.standard_normal((2, N, N)) + 1j * rng.standard_normal((2, N, N))).astype(np.complex64)
+    M = plan.degrid(torch.from_numpy(Gin).cuda()).cpu().numpy()
+    Mref = O.degrid(geom, Gin.astype(np.complex128))
+    for c in range(2):
+        assert rel_l2(G[c], Gref[c]) <= BF16X3_RTOL
+        assert rel_l2(M[c], Mref[c]) <= BF16X3_RTOL
