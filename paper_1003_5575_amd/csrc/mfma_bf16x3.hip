@@ -42,6 +42,7 @@ typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
 typedef short s4_t __attribute__((ext_vector_type(4)));
 typedef unsigned u4_t __attribute__((ext_vector_type(4)));
 typedef unsigned u2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u4w_t __attribute__((ext_vector_type(4), aligned(4)));   // 16 bytes, word-aligned
 
 constexpr int kMT = 16;          // subtile edge (one MFMA output block)
 constexpr int kQueue = 128;      // listing queue per wave (at most chunk - 1 + 64 entries)
@@ -455,11 +456,12 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     {
       uint32_t t0, t1, t2, t3;
       if (PB) {
-        const uint32_t ya = ds[i16].x + 4u * g;
-        t0 = pb.thl[ya];
-        t1 = pb.thl[ya + 1];
-        t2 = pb.thl[ya + 2];
-        t3 = pb.thl[ya + 3];
+        // four consecutive words at any word offset: a 16-byte load with 4-byte alignment
+        const u4w_t t = *reinterpret_cast<const u4w_t *>(pb.thl + ds[i16].x + 4u * g);
+        t0 = t[0];
+        t1 = t[1];
+        t2 = t[2];
+        t3 = t[3];
       } else {
         const uint32_t ya = ds[i16].x + 16u * g;
         t0 = lds_u32(lds, ya);
