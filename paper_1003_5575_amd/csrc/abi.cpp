@@ -606,6 +606,9 @@ rts_status rts_plan_set_baseline_kernels(rts_plan_t plan, const float *tab, void
     return RTS_OK;
   }
   RTS_REQUIRE(aligned(tab, 4), "tab must be 4-byte aligned");
+  // the kernels address the tables with 32-bit word offsets
+  RTS_REQUIRE(pb_table_words(*plan) < ((int64_t)1 << 32), "per-baseline tables of %d baselines exceed 2^32 words",
+              plan->B);
   if (!plan->d_pb_thl) {
     const size_t words = (size_t)pb_table_words(*plan);
     RTS_HIP(dalloc(&plan->d_pb_thl, words));
