@@ -64,7 +64,7 @@ typedef enum {
 
 typedef enum {
   RTS_PREC_FP32 = 0,    /* FP32 arithmetic, FP64 tile accumulation (all entry points) */
-  RTS_PREC_BF16X3 = 1   /* rts_grid and rts_degrid on the matrix cores (Eq. (1) and its adjoint
+  RTS_PREC_BF16X3 = 1,  /* rts_grid and rts_degrid on the matrix cores (Eq. (1) and its adjoint
                            per 16x16-cell tile): gridding is the contraction Av^T diag(wV) Au over
                            the tile's samples, degridding H = Av G_tile followed by the k_x sum,
                            with per-tile partial values added to the model with FP32 atomics.
@@ -73,6 +73,9 @@ typedef enum {
                            1e-6).  The plan's tile (a multiple of 16 cells) is split into 16x16
                            subtiles, one wave each.  The fused step of such a plan uses the FP32
                            kernels. */
+  RTS_PREC_FP32_MFMA = 2  /* as RTS_PREC_BF16X3, with FP32 operands (v_mfma_f32_16x16x4_f32,
+                           FP32 accumulation): FP32 results on the matrix cores for wide
+                           kernels (supports up to 24, per-baseline kernels) */
 } rts_precision;
 
 typedef enum {

@@ -57,7 +57,7 @@ def _check_dev(t, name, dtype, shape=None):
     return t
 
 
-PRECISIONS = {"fp32": 0, "bf16x3": 1}
+PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp32_mfma": 2}
 SCHEDULES = {"auto": 0, "tiles": 1, "persistent": 2}
 
 
@@ -169,7 +169,8 @@ class GridPlan:
     def set_baseline_kernels(self, tab, stream=None):
         """Per-visibility kernels (rts_plan_set_baseline_kernels): ``tab`` float32
         [B, OS, W] on the device, baseline b's separable kernel sampled in the
-        layout of ``table``; None restores the shared kernel.  BF16x3 plans only."""
+        layout of ``table``; None restores the shared kernel.  Matrix-core plans only
+        (precision "bf16x3" or "fp32_mfma")."""
         torch = _torch()
         if tab is None:
             _lib.check(_lib.load().rts_plan_set_baseline_kernels(self.handle, None, _stream(stream)),

@@ -83,7 +83,7 @@ rts_status validate(const rts_params *p) {
   RTS_REQUIRE(p != nullptr, "params is NULL");
   RTS_REQUIRE(p->n_grid >= 16 && p->n_grid <= kMaxN && p->n_grid % 2 == 0,
               "n_grid must be even and in [16, %d] (got %d)", kMaxN, p->n_grid);
-  const int wmax = p->precision == RTS_PREC_BF16X3 ? kMaxWMfma : kMaxW;
+  const int wmax = mfma_precision(p->precision) ? kMaxWMfma : kMaxW;
   RTS_REQUIRE(p->support >= 2 && p->support <= wmax, "support must be in [2, %d] for this precision (got %d)",
               wmax, p->support);
   RTS_REQUIRE(p->oversample >= 1 && p->oversample <= kMaxOS, "oversample must be in [1, %d] (got %d)",
@@ -93,16 +93,16 @@ rts_status validate(const rts_params *p) {
   RTS_REQUIRE(std::isfinite(p->cell_lambda) && p->cell_lambda > 0.0, "cell_lambda must be > 0");
   RTS_REQUIRE(std::isfinite(p->beta), "beta must be finite");
   RTS_REQUIRE(p->conjugate == 0 || p->conjugate == 1, "conjugate must be 0 or 1");
-  RTS_REQUIRE(p->precision == RTS_PREC_FP32 || p->precision == RTS_PREC_BF16X3, "precision %d is not available",
+  RTS_REQUIRE(p->precision == RTS_PREC_FP32 || mfma_precision(p->precision), "precision %d is not available",
               p->precision);
   RTS_REQUIRE(p->schedule >= RTS_SCHEDULE_AUTO && p->schedule <= RTS_SCHEDULE_PERSISTENT,
               "schedule %d is not available", p->schedule);
   const int64_t n = (int64_t)p->n_chan * p->n_base * p->n_time * (1 + p->conjugate);
   RTS_REQUIRE(n < ((int64_t)1 << 31), "n_chan*n_base*n_time*(1+conjugate) must be < 2^31");
   RTS_REQUIRE(p->n_grid >= p->support + 2, "n_grid must be at least support + 2");
-  if (p->precision == RTS_PREC_BF16X3) {
-    RTS_REQUIRE(p->n_grid % 16 == 0, "BF16x3 plans need n_grid divisible by 16");
-    RTS_REQUIRE(p->tile == 0 || p->tile % 16 == 0, "BF16x3 plans need a tile that is a multiple of 16 (got %d)",
+  if (mfma_precision(p->precision)) {
+    RTS_REQUIRE(p->n_grid % 16 == 0, "matrix-core plans need n_grid divisible by 16");
+    RTS_REQUIRE(p->tile == 0 || p->tile % 16 == 0, "matrix-core plans need a tile that is a multiple of 16 (got %d)",
                 p->tile);
   }
   if (p->tile != 0) {
@@ -376,7 +376,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   P->beta = params->beta > 0.0 ? params->beta : 2.34 * P->W;
   P->precision = params->precision;
   P->tile = params->tile ? params->tile : choose_tile(P->N, P->WN);   // 64, 32 or 16
-  if (P->tile == 0 || (P->precision == RTS_PREC_BF16X3 && P->tile % 16 != 0)) {
+  if (P->tile == 0 || (mfma_precision(P->precision) && P->tile % 16 != 0)) {
     set_error("no legal tile size for n_grid=%d support=%d", P->N, P->W);
     return RTS_E_UNSUPPORTED;
   }
@@ -390,7 +390,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
     set_error("support %d is not instantiated", P->W);
     return RTS_E_UNSUPPORTED;
   }
-  if (P->precision == RTS_PREC_BF16X3 && mfma_lds_bytes(P->WN, 2 * P->OS, P->tile) > 65536) {
+  if (mfma_precision(P->precision) && mfma_lds_bytes(P->WN, 2 * P->OS, P->tile) > 65536) {
     set_error("support %d, oversample %d and tile %d need more than 64 KiB of LDS on the matrix-core path",
               P->W, P->OS, P->tile);
     return RTS_E_UNSUPPORTED;
@@ -425,7 +425,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
   // about 20 per workgroup slot), where a few dense tiles otherwise run last;
   // with more tiles the tail is short and the ordering pass costs more than it
   // saves.
-  const bool mfma_order = P->precision == RTS_PREC_BF16X3 && P->nkeys <= (int64_t)64 * P->n_cu;
+  const bool mfma_order = mfma_precision(P->precision) && P->nkeys <= (int64_t)64 * P->n_cu;
   if (P->schedule == RTS_SCHEDULE_PERSISTENT || mfma_order) {
     RTS_HIP(dalloc(&P->d_order, (size_t)P->nkeys));
     RTS_HIP(dalloc(&P->d_lpt, (size_t)kLptWords));
@@ -509,7 +509,7 @@ rts_status rts_grid(rts_plan_t plan, const float *vis, const float *weights, flo
   a.w = weights;
   a.gout = (float2 *)grid;
   a.vec = vector_ok(*plan, vis, weights, nullptr);
-  if (plan->precision == RTS_PREC_BF16X3)
+  if (mfma_precision(plan->precision))
     RTS_HIP(launch_grid_mfma(*plan, a, (hipStream_t)stream));
   else
     RTS_HIP(launch_tile(kGrid, *plan, a, (hipStream_t)stream));
@@ -524,7 +524,7 @@ rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *
   a.gin = (const float2 *)grid;
   a.model = (float2 *)vis_out;
   a.vec = vector_ok(*plan, nullptr, nullptr, vis_out);
-  if (plan->precision == RTS_PREC_BF16X3)
+  if (mfma_precision(plan->precision))
     RTS_HIP(launch_degrid_mfma(*plan, a, (hipStream_t)stream));
   else
     RTS_HIP(launch_tile(kDegrid, *plan, a, (hipStream_t)stream));
@@ -594,8 +594,8 @@ rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream) {
 
 rts_status rts_plan_set_baseline_kernels(rts_plan_t plan, const float *tab, void *stream) {
   if (rts_status st = check_plan(plan)) return st;
-  if (plan->precision != RTS_PREC_BF16X3) {
-    set_error("per-baseline kernels need a BF16x3 plan");
+  if (!mfma_precision(plan->precision)) {
+    set_error("per-baseline kernels need a matrix-core plan (BF16x3 or FP32 on the matrix cores)");
     return RTS_E_UNSUPPORTED;
   }
   if (!tab) {

@@ -107,7 +107,7 @@ __device__ __forceinline__ uint32_t highs(uint32_t w0, uint32_t w1) { return __b
 // place the WN weights of each phase row, 32 threads per row.
 __device__ __forceinline__ const char *load_padded_tables(const TileArgs &a, const uint16_t *tab_hi,
                                                           const uint16_t *tab_lo, const PadGeom &pg, int RH,
-                                                          int RW) {
+                                                          int RW, bool f32) {
   extern __shared__ float4 smem4[];
   const int n4 = (pg.TX + pg.TA + 3) >> 2;
   for (int i = threadIdx.x; i < n4; i += blockDim.x) smem4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -119,7 +119,8 @@ __device__ __forceinline__ const char *load_padded_tables(const TileArgs &a, con
     if (t < a.WN) {
       const int src = r * a.WNP + t;
       tab[RW + r * pg.SX + t] = a.tabE[src];
-      thl[RH + r * pg.SA + t] = (uint32_t)tab_hi[src] | ((uint32_t)tab_lo[src] << 16);
+      thl[RH + r * pg.SA + t] = f32 ? __float_as_uint(a.tabE[src])
+                                    : (uint32_t)tab_hi[src] | ((uint32_t)tab_lo[src] << 16);
     }
   }
   __syncthreads();
@@ -222,7 +223,7 @@ __device__ __forceinline__ void slot_offsets_pb(const TileArgs &a, const PbTable
 // by the GR row blocks.  One v_mfma_f32_16x16x32_bf16 per term and block: K
 // runs over 32 sample slots.  Registers are capped at 80 so that three
 // workgroups of 8 waves share a CU.
-template <int GR, bool PB>
+template <int GR, bool PB, bool F32>
 __global__ __launch_bounds__(64 * max_waves<GR>()) __attribute__((amdgpu_waves_per_eu(6)))
 void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_lo, PbTables pb) {
   constexpr int kChunk = 32;                         // sample slots per MFMA K step
@@ -232,7 +233,7 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
   const int key = tile_key(a);
   if (key < 0) return;
   const PadGeom pg = pad_geom(a.WN, a.OS2, RH, RW);
-  const char *lds = PB ? nullptr : load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
+  const char *lds = PB ? nullptr : load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW, F32);
 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int nwx = a.tile / RW;                      // regions per tile row
@@ -290,54 +291,80 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
 
-    // Operands.  A_rb[y][s] = ky_s(y0 + 16 rb + y), row y = i16, samples s = 8g + e.
-    // B[s][x] = a_s kx_s(x0 + x), column x = i16, the same samples.
-    u4_t ah[GR], al[GR], brh, brl, bih, bil;
+    if constexpr (F32) {
+      // FP32 operands, one v_mfma_f32_16x16x4_f32 per term, row block and step of
+      // 4 samples s = 4 st + g: A_rb[y][g] = ky_s(y0 + 16 rb + y) in lane y + 16g,
+      // B[g][x] = a_s kx_s(x0 + x) in lane x + 16g.
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      uint32_t av[GR][2];
-      float kx[2], ar[2], ai[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint4 sl = ss[8 * g + 2 * p + h];
+      for (int st = 0; st < kChunk / 4; ++st) {
+        const uint4 sl = ss[4 * st + g];
+        float av[GR], kx;
         if (PB) {
-          const uint32_t ya = sl.x + i16, xa = sl.y + i16;
 #pragma unroll
-          for (int rb = 0; rb < GR; ++rb) av[rb][h] = pb.thl[ya + kMT * rb];
-          kx[h] = pb.tab[xa];
+          for (int rb = 0; rb < GR; ++rb) av[rb] = __uint_as_float(pb.thl[sl.x + i16 + kMT * rb]);
+          kx = pb.tab[sl.y + i16];
         } else {
-          const uint32_t ya = sl.x + 4u * i16, xa = sl.y + 4u * i16;
 #pragma unroll
-          for (int rb = 0; rb < GR; ++rb) av[rb][h] = lds_u32(lds, ya + 4u * kMT * rb);
-          kx[h] = lds_f32(lds, xa);
+          for (int rb = 0; rb < GR; ++rb) av[rb] = lds_f32(lds, sl.x + 4u * i16 + 4u * kMT * rb);
+          kx = lds_f32(lds, sl.y + 4u * i16);
         }
-        ar[h] = __uint_as_float(sl.z);
-        ai[h] = __uint_as_float(sl.w);
-      }
+        const float br = __uint_as_float(sl.z) * kx, bi = __uint_as_float(sl.w) * kx;
 #pragma unroll
+        for (int rb = 0; rb < GR; ++rb) {
+          acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb], br, acc_re[rb], 0, 0, 0);
+          acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb], bi, acc_im[rb], 0, 0, 0);
+        }
+      }
+    } else {
+      // Operands.  A_rb[y][s] = ky_s(y0 + 16 rb + y), row y = i16, samples s = 8g + e.
+      // B[s][x] = a_s kx_s(x0 + x), column x = i16, the same samples.
+      u4_t ah[GR], al[GR], brh, brl, bih, bil;
+  #pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        uint32_t av[GR][2];
+        float kx[2], ar[2], ai[2];
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint4 sl = ss[8 * g + 2 * p + h];
+          if (PB) {
+            const uint32_t ya = sl.x + i16, xa = sl.y + i16;
+  #pragma unroll
+            for (int rb = 0; rb < GR; ++rb) av[rb][h] = pb.thl[ya + kMT * rb];
+            kx[h] = pb.tab[xa];
+          } else {
+            const uint32_t ya = sl.x + 4u * i16, xa = sl.y + 4u * i16;
+  #pragma unroll
+            for (int rb = 0; rb < GR; ++rb) av[rb][h] = lds_u32(lds, ya + 4u * kMT * rb);
+            kx[h] = lds_f32(lds, xa);
+          }
+          ar[h] = __uint_as_float(sl.z);
+          ai[h] = __uint_as_float(sl.w);
+        }
+  #pragma unroll
+        for (int rb = 0; rb < GR; ++rb) {
+          ah[rb][p] = lows(av[rb][0], av[rb][1]);
+          al[rb][p] = highs(av[rb][0], av[rb][1]);
+        }
+        uint32_t hh, ll;
+        split_pair(ar[0], kx[0], ar[1], kx[1], hh, ll);
+        brh[p] = hh;
+        brl[p] = ll;
+        split_pair(ai[0], kx[0], ai[1], kx[1], hh, ll);
+        bih[p] = hh;
+        bil[p] = ll;
+      }
+      const bf8_t Brh = __builtin_bit_cast(bf8_t, brh), Brl = __builtin_bit_cast(bf8_t, brl);
+      const bf8_t Bih = __builtin_bit_cast(bf8_t, bih), Bil = __builtin_bit_cast(bf8_t, bil);
+  #pragma unroll
       for (int rb = 0; rb < GR; ++rb) {
-        ah[rb][p] = lows(av[rb][0], av[rb][1]);
-        al[rb][p] = highs(av[rb][0], av[rb][1]);
+        const bf8_t Ah = __builtin_bit_cast(bf8_t, ah[rb]), Al = __builtin_bit_cast(bf8_t, al[rb]);
+        acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Brh, acc_re[rb], 0, 0, 0);
+        acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Brl, acc_re[rb], 0, 0, 0);
+        acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Brh, acc_re[rb], 0, 0, 0);
+        acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bih, acc_im[rb], 0, 0, 0);
+        acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bil, acc_im[rb], 0, 0, 0);
+        acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bih, acc_im[rb], 0, 0, 0);
       }
-      uint32_t hh, ll;
-      split_pair(ar[0], kx[0], ar[1], kx[1], hh, ll);
-      brh[p] = hh;
-      brl[p] = ll;
-      split_pair(ai[0], kx[0], ai[1], kx[1], hh, ll);
-      bih[p] = hh;
-      bil[p] = ll;
-    }
-    const bf8_t Brh = __builtin_bit_cast(bf8_t, brh), Brl = __builtin_bit_cast(bf8_t, brl);
-    const bf8_t Bih = __builtin_bit_cast(bf8_t, bih), Bil = __builtin_bit_cast(bf8_t, bil);
-#pragma unroll
-    for (int rb = 0; rb < GR; ++rb) {
-      const bf8_t Ah = __builtin_bit_cast(bf8_t, ah[rb]), Al = __builtin_bit_cast(bf8_t, al[rb]);
-      acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Brh, acc_re[rb], 0, 0, 0);
-      acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Brl, acc_re[rb], 0, 0, 0);
-      acc_re[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Brh, acc_re[rb], 0, 0, 0);
-      acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bih, acc_im[rb], 0, 0, 0);
-      acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bil, acc_im[rb], 0, 0, 0);
-      acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bih, acc_im[rb], 0, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();   // the next chunk's slot writes follow these reads
   });
@@ -377,7 +404,7 @@ __device__ __forceinline__ float dpp_xor1(float v) {
 // model value over the region is sum_x H[s][x] k_x(x).  A window crossing
 // region edges is covered by every region it touches, so the partial values are
 // added to the (zeroed) model with FP32 atomics.
-template <int DC, bool PB>
+template <int DC, bool PB, bool F32>
 __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
                                                                              const uint16_t *tab_lo, PbTables pb) {
   constexpr int kChunk = 16;
@@ -387,7 +414,7 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
   const int key = tile_key(a);
   if (key < 0) return;
   const PadGeom pg = pad_geom(a.WN, a.OS2, RH, RW);
-  const char *lds = PB ? nullptr : load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW);
+  const char *lds = PB ? nullptr : load_padded_tables(a, tab_hi, tab_lo, pg, RH, RW, F32);
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nwx = a.tile / RW;                      // regions per tile row
@@ -400,11 +427,25 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
   const int i16 = lane & 15, g = lane >> 4;
   const uint32_t empty_ya = PB ? 0u : 4u * (uint32_t)pg.TX, empty_xa = 0u;
 
-  // B operands, loaded once: lane (x = i16, g) of block cb holds rows 4g + e of
-  // Re G and Im G at region column 16 cb + x, split into hi and lo parts.
+  // B operands, loaded once.  BF16x3: lane (x = i16, g) of block cb holds rows
+  // 4g + e of Re G and Im G at region column 16 cb + x, split into hi and lo
+  // parts.  FP32: lane (x, g) holds row 4t + g of K step t (gre, gim).
   s4_t brh[DC], brl[DC], bih[DC], bil[DC];
+  float gre[DC][4], gim[DC][4];
+  if (F32) {
 #pragma unroll
-  for (int cb = 0; cb < DC; ++cb) {
+    for (int cb = 0; cb < DC; ++cb) {
+      const float2 *gt = a.gin + ((size_t)c * a.N + y0 + g) * a.N + x0 + kMT * cb + i16;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float2 v = gt[(size_t)(4 * t) * a.N];
+        gre[cb][t] = v.x;
+        gim[cb][t] = v.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int cb = 0; cb < (F32 ? 0 : DC); ++cb) {
     const float2 *gt = a.gin + ((size_t)c * a.N + y0 + 4 * g) * a.N + x0 + kMT * cb + i16;
     uint32_t sr[4], si[4];
 #pragma unroll
@@ -451,37 +492,53 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
 
-    // A operand: lane (s = i16, g) holds k_y of sample s at region rows 4g + e.
-    s4_t ah, al;
-    {
-      uint32_t t0, t1, t2, t3;
-      if (PB) {
-        // four consecutive words at any word offset: a 16-byte load with 4-byte alignment
-        const u4w_t t = *reinterpret_cast<const u4w_t *>(pb.thl + ds[i16].x + 4u * g);
-        t0 = t[0];
-        t1 = t[1];
-        t2 = t[2];
-        t3 = t[3];
-      } else {
-        const uint32_t ya = ds[i16].x + 16u * g;
-        t0 = lds_u32(lds, ya);
-        t1 = lds_u32(lds, ya + 4u);
-        t2 = lds_u32(lds, ya + 8u);
-        t3 = lds_u32(lds, ya + 12u);
-      }
-      ah = __builtin_bit_cast(s4_t, u2_t{lows(t0, t1), lows(t2, t3)});
-      al = __builtin_bit_cast(s4_t, u2_t{highs(t0, t1), highs(t2, t3)});
-    }
     f4_t hr[DC], hi[DC];
+    if constexpr (F32) {
+      // FP32: K step t covers region rows 4t + g; A[s][g] = k_y of sample s = i16.
+      const uint32_t ya = ds[i16].x;
 #pragma unroll
-    for (int cb = 0; cb < DC; ++cb) {
-      const f4_t z = {0.0f, 0.0f, 0.0f, 0.0f};
-      hr[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, brh[cb], z, 0, 0, 0);
-      hr[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, brl[cb], hr[cb], 0, 0, 0);
-      hr[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, brh[cb], hr[cb], 0, 0, 0);
-      hi[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bih[cb], z, 0, 0, 0);
-      hi[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bil[cb], hi[cb], 0, 0, 0);
-      hi[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bih[cb], hi[cb], 0, 0, 0);
+      for (int cb = 0; cb < DC; ++cb) hr[cb] = hi[cb] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float av = PB ? __uint_as_float(pb.thl[ya + 4u * t + g]) : lds_f32(lds, ya + 4u * (4u * t + g));
+#pragma unroll
+        for (int cb = 0; cb < DC; ++cb) {
+          hr[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, gre[cb][t], hr[cb], 0, 0, 0);
+          hi[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, gim[cb][t], hi[cb], 0, 0, 0);
+        }
+      }
+    } else {
+      // A operand: lane (s = i16, g) holds k_y of sample s at region rows 4g + e.
+      s4_t ah, al;
+      {
+        uint32_t t0, t1, t2, t3;
+        if (PB) {
+          // four consecutive words at any word offset: a 16-byte load with 4-byte alignment
+          const u4w_t t = *reinterpret_cast<const u4w_t *>(pb.thl + ds[i16].x + 4u * g);
+          t0 = t[0];
+          t1 = t[1];
+          t2 = t[2];
+          t3 = t[3];
+        } else {
+          const uint32_t ya = ds[i16].x + 16u * g;
+          t0 = lds_u32(lds, ya);
+          t1 = lds_u32(lds, ya + 4u);
+          t2 = lds_u32(lds, ya + 8u);
+          t3 = lds_u32(lds, ya + 12u);
+        }
+        ah = __builtin_bit_cast(s4_t, u2_t{lows(t0, t1), lows(t2, t3)});
+        al = __builtin_bit_cast(s4_t, u2_t{highs(t0, t1), highs(t2, t3)});
+      }
+  #pragma unroll
+      for (int cb = 0; cb < DC; ++cb) {
+        const f4_t z = {0.0f, 0.0f, 0.0f, 0.0f};
+        hr[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, brh[cb], z, 0, 0, 0);
+        hr[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, brl[cb], hr[cb], 0, 0, 0);
+        hr[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, brh[cb], hr[cb], 0, 0, 0);
+        hi[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bih[cb], z, 0, 0, 0);
+        hi[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bil[cb], hi[cb], 0, 0, 0);
+        hi[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bih[cb], hi[cb], 0, 0, 0);
+      }
     }
 
     // H_cb[s][x] sits in lane x + 16 (s / 4), register s % 4.  Weight by k_x and
@@ -538,7 +595,8 @@ PbTables pb_tables(const Plan &P) {
 }
 
 // Per-baseline padded rows from the caller's [B][OS][W] table (layout above).
-__global__ void k_build_pb_tables(const float *__restrict__ tab, int64_t total, int OS, int W, int WN, PbTables pb) {
+__global__ void k_build_pb_tables(const float *__restrict__ tab, int64_t total, int OS, int W, int WN, PbTables pb,
+                                  int f32) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= total) return;
   const int per = 2 * OS * WN;
@@ -550,7 +608,8 @@ __global__ void k_build_pb_tables(const float *__restrict__ tab, int64_t total, 
   pb.tab[b * pb.TX + kPbPad + srow * pb.SX + i] = v;
   const __bf16 h = (__bf16)v;
   const __bf16 l = (__bf16)(v - (float)h);
-  const uint32_t w = (uint32_t)__builtin_bit_cast(uint16_t, h) | ((uint32_t)__builtin_bit_cast(uint16_t, l) << 16);
+  const uint32_t w = f32 ? __float_as_uint(v)
+                         : (uint32_t)__builtin_bit_cast(uint16_t, h) | ((uint32_t)__builtin_bit_cast(uint16_t, l) << 16);
   pb.thl[b * pb.TA + kPbPad + srow * pb.SA + i] = w;
 }
 
@@ -579,7 +638,7 @@ hipError_t build_baseline_tables(const Plan &P, const float *tab, hipStream_t s)
   if (e != hipSuccess) return e;
   const int64_t total = (int64_t)P.B * 2 * P.OS * P.WN;
   hipLaunchKernelGGL(k_build_pb_tables, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, tab, total, P.OS,
-                     P.W, P.WN, pb);
+                     P.W, P.WN, pb, (int)(P.precision == RTS_PREC_FP32_MFMA));
   return hipGetLastError();
 }
 
@@ -589,25 +648,44 @@ static unsigned mfma_grid_size(const Plan &P, const TileArgs &a) {
   return a.order ? (unsigned)(8 * ((P.nkeys + 7) / 8)) : (unsigned)P.nkeys;
 }
 
-// Regions of two subtiles per wave where the tile edge is a multiple of 32.
+template <int NR, bool PB, bool F32>
+void launch_grid_variant(const Plan &P, const TileArgs &a, hipStream_t s, const PbTables &pb, unsigned threads,
+                         size_t lds) {
+  hipLaunchKernelGGL((k_grid_mfma_bf16x3<NR, PB, F32>), dim3(mfma_grid_size(P, a)), dim3(threads), lds, s, a,
+                     P.d_tab_hi, P.d_tab_lo, pb);
+}
+
+template <int NR, bool PB, bool F32>
+void launch_degrid_variant(const Plan &P, const TileArgs &a, hipStream_t s, const PbTables &pb, unsigned threads,
+                           size_t lds) {
+  hipLaunchKernelGGL((k_degrid_mfma_bf16x3<NR, PB, F32>), dim3(mfma_grid_size(P, a)), dim3(threads), lds, s, a,
+                     P.d_tab_hi, P.d_tab_lo, pb);
+}
+
+// The kernel variant for (regions of two subtiles when the tile edge is a
+// multiple of 32, per-baseline tables, FP32 operands).
+#define RTS_MFMA_PICK(fn)                                                                                       \
+  do {                                                                                                         \
+    const int code = (pair == 2 ? 4 : 0) | (pbk ? 2 : 0) | (f32 ? 1 : 0);                                      \
+    switch (code) {                                                                                            \
+      case 0: fn<1, false, false>(P, a, s, pb, threads, lds); break;                                          \
+      case 1: fn<1, false, true>(P, a, s, pb, threads, lds); break;                                           \
+      case 2: fn<1, true, false>(P, a, s, pb, threads, lds); break;                                           \
+      case 3: fn<1, true, true>(P, a, s, pb, threads, lds); break;                                            \
+      case 4: fn<2, false, false>(P, a, s, pb, threads, lds); break;                                          \
+      case 5: fn<2, false, true>(P, a, s, pb, threads, lds); break;                                           \
+      case 6: fn<2, true, false>(P, a, s, pb, threads, lds); break;                                           \
+      default: fn<2, true, true>(P, a, s, pb, threads, lds); break;                                           \
+    }                                                                                                          \
+  } while (0)
+
 hipError_t launch_grid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   const int pair = P.tile % (2 * kMT) == 0 ? 2 : 1;
   const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT) / pair);
-  const bool pbk = P.d_pb_thl != nullptr;
+  const bool pbk = P.d_pb_thl != nullptr, f32 = P.precision == RTS_PREC_FP32_MFMA;
   const size_t lds = pbk ? 0 : padded_lds_bytes(a, pair * kMT, kMT);
   const PbTables pb = pb_tables(P);
-  const dim3 grid(mfma_grid_size(P, a)), block(threads);
-  if (pair == 2) {
-    if (pbk)
-      hipLaunchKernelGGL((k_grid_mfma_bf16x3<2, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
-    else
-      hipLaunchKernelGGL((k_grid_mfma_bf16x3<2, false>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
-  } else {
-    if (pbk)
-      hipLaunchKernelGGL((k_grid_mfma_bf16x3<1, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
-    else
-      hipLaunchKernelGGL((k_grid_mfma_bf16x3<1, false>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
-  }
+  RTS_MFMA_PICK(launch_grid_variant);
   return hipGetLastError();
 }
 
@@ -617,21 +695,10 @@ hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int pair = P.tile % (2 * kMT) == 0 ? 2 : 1;
   const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT) / pair);
-  const bool pbk = P.d_pb_thl != nullptr;
+  const bool pbk = P.d_pb_thl != nullptr, f32 = P.precision == RTS_PREC_FP32_MFMA;
   const size_t lds = pbk ? 0 : padded_lds_bytes(a, kMT, pair * kMT);
   const PbTables pb = pb_tables(P);
-  const dim3 grid(mfma_grid_size(P, a)), block(threads);
-  if (pair == 2) {
-    if (pbk)
-      hipLaunchKernelGGL((k_degrid_mfma_bf16x3<2, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
-    else
-      hipLaunchKernelGGL((k_degrid_mfma_bf16x3<2, false>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
-  } else {
-    if (pbk)
-      hipLaunchKernelGGL((k_degrid_mfma_bf16x3<1, true>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
-    else
-      hipLaunchKernelGGL((k_degrid_mfma_bf16x3<1, false>), grid, block, lds, s, a, P.d_tab_hi, P.d_tab_lo, pb);
-  }
+  RTS_MFMA_PICK(launch_degrid_variant);
   return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ def plan_call(lib, p, uvw=1, freq=(150e6, 151e6), w=1):
     ("n_chan", 0, "n_chan"), ("n_base", 0, "n_chan"), ("n_time", 0, "n_chan"),
     ("cell_lambda", 0.0, "cell_lambda"), ("cell_lambda", float("nan"), "cell_lambda"),
     ("beta", float("inf"), "beta"),
-    ("conjugate", 2, "conjugate"), ("precision", 7, "precision"), ("precision", 2, "precision"), ("schedule", 3, "schedule"), ("schedule", -1, "schedule"),
+    ("conjugate", 2, "conjugate"), ("precision", 7, "precision"), ("precision", 3, "precision"), ("schedule", 3, "schedule"), ("schedule", -1, "schedule"),
     ("tile", 48, "tile"), ("tile", 4, "tile"), ("tile", 128, "tile"), ("tile", 7, "tile"),
 ])
 def test_invalid_params_rejected_on_host(lib, field, value, msg):

@@ -109,3 +109,22 @@ def test_polconvert_empty(rts):
     A = torch.zeros((16, 0), dtype=torch.complex64, device="cuda")
     P = torch.zeros((3, 4, 0), dtype=torch.complex64, device="cuda")
     assert rts.polconvert(A, P).shape == (3, 4, 0)
+
+
+@pytest.mark.parametrize("gap", [0, 2, 3])
+def test_polconvert_channel_stride_through_the_abi(rts, gap):
+    """Per-channel matrix blocks a_chan_stride = 16 n + gap complex elements apart
+    (gap 3 makes the stride odd: the one-pixel path), called through the C ABI."""
+    n, C = 1000, 3
+    A, P = make_polconv_inputs(n, C, seed=30 + gap, per_channel=True)
+    stride = 16 * n + gap
+    buf = torch.zeros(C * stride, dtype=torch.complex64, device="cuda")
+    for c in range(C):
+        buf[c * stride:c * stride + 16 * n] = torch.from_numpy(A[c].ravel()).cuda()
+    Pd = torch.from_numpy(P).cuda()
+    S = torch.empty_like(Pd)
+    lib = rts._lib.load()
+    st = lib.rts_polconvert(buf.data_ptr(), Pd.data_ptr(), S.data_ptr(), n, C, stride, None)
+    torch.cuda.synchronize()
+    assert st == 0
+    check(S.cpu().numpy(), A, P)
