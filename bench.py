@@ -443,6 +443,18 @@ def bench_mixed(args, torch, rts, make_workload):
     ms32, (p32, g32, d32) = timed(plan32, K)
     tile32 = plan32.info["tile"]
     plan32.close()
+    # FP32 operands on the matrix cores, same inputs; error on the same channels
+    planm = rts.GridPlan(uvw, wl.freq_hz, w, N, wl.cell_lambda, support=W, oversample=OS, precision="fp32_mfma")
+    msm, (pm, gm, dm) = timed(planm, K)
+    planm.close()
+    errs_m = None
+    if errs is not None:
+        Gm = gout[chans].cpu().numpy()
+        Mm = model[chans].cpu().numpy()
+        errs_m = {"channels": errs["channels"],
+                  "grid_rel_l2": [float(np.linalg.norm(Gm[i] - Go[i]) / np.linalg.norm(Go[i])) for i in range(len(chans))],
+                  "degrid_rel_l2": [float(np.linalg.norm(Mm[i] - Mo[i]) / np.linalg.norm(Mo[i])) for i in range(len(chans))]}
+        log(f"[bench] mixed fp32_mfma errors: {errs_m}")
     nl = info["n_listings"]
     out = {
         "metric": METRIC, "value": round(n_valid / ms / 1e3, 1), "unit": "Mvis/s", "n_gpus": 1, "steps": K,
@@ -455,6 +467,9 @@ def bench_mixed(args, torch, rts, make_workload):
                       "n_listings": nl, "seg_max": info["seg_max"]},
         "fp32_path": {"ms_per_step": round(ms32, 4), "value": round(n_valid / ms32 / 1e3, 1), "tile": tile32,
                       "plan_ms": round(p32, 4), "grid_ms": round(g32, 4), "degrid_ms": round(d32, 4)},
+        "fp32_mfma_path": {"ms_per_step": round(msm, 4), "value": round(n_valid / msm / 1e3, 1),
+                           "plan_ms": round(pm, 4), "grid_ms": round(gm, 4), "degrid_ms": round(dm, 4),
+                           "error": errs_m},
         "bf16x3_error": errs,
     }
     print(json.dumps(out), flush=True)
@@ -515,6 +530,11 @@ def bench_pervis(args, torch, rts, make_workload):
     plan.set_baseline_kernels(None)
     ms_sh, (_, g_sh, d_sh) = timed(K)
     plan.close()
+    # FP32 operands on the matrix cores, per-baseline kernels
+    plan = rts.GridPlan(uvw, wl.freq_hz, w, N, wl.cell_lambda, support=W, oversample=OS, precision="fp32_mfma")
+    plan.set_baseline_kernels(tab)
+    ms_m, (_, g_m, d_m) = timed(K)
+    plan.close()
     # algorithmic bytes of grid + degrid: visibilities and weights read and model
     # written (20 B per valid sample), the grids written, the touched cells read,
     # and the per-baseline tables once
@@ -558,6 +578,7 @@ def bench_pervis(args, torch, rts, make_workload):
         "breakdown": {"plan_ms": round(plan_ms, 4), "grid_ms": round(g_ms, 4), "degrid_ms": round(d_ms, 4),
                       "n_listings": info["n_listings"], "seg_max": info["seg_max"]},
         "shared_kernel": {"ms_per_step": round(ms_sh, 4), "grid_ms": round(g_sh, 4), "degrid_ms": round(d_sh, 4)},
+        "fp32_mfma": {"ms_per_step": round(ms_m, 4), "grid_ms": round(g_m, 4), "degrid_ms": round(d_m, 4)},
         "roofline": {"bound": "hbm", "achieved": round(alg / kms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(alg / kms / 1e6 / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_grid_mfma_bf16x3<2, true> + k_degrid_mfma_bf16x3<2, true>",

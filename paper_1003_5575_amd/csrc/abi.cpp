@@ -79,6 +79,9 @@ float bf16_value(uint16_t b) {
   return f;
 }
 
+// Plans whose rts_grid / rts_degrid run the matrix-core kernels.
+bool mfma_precision(int p) { return p == RTS_PREC_BF16X3 || p == RTS_PREC_FP32_MFMA; }
+
 rts_status validate(const rts_params *p) {
   RTS_REQUIRE(p != nullptr, "params is NULL");
   RTS_REQUIRE(p->n_grid >= 16 && p->n_grid <= kMaxN && p->n_grid % 2 == 0,

@@ -13,9 +13,7 @@
 namespace rts {
 
 constexpr int kMaxW = 16;
-constexpr int kMaxWMfma = 24;   // supports up to this on the matrix-core path
-// Plans whose rts_grid / rts_degrid run the matrix-core kernels.
-inline bool mfma_precision(int p) { return p == RTS_PREC_BF16X3 || p == RTS_PREC_FP32_MFMA; }
+constexpr int kMaxWMfma = 24;   // supports up to this on the matrix-core path (BF16x3 plans)
 constexpr int kMaxOS = 64;
 constexpr int kMaxN = 8192;
 constexpr int kMaxTile = 64;     // FP64 tile accumulator: 16*64*64 B = 64 KiB of LDS

@@ -8,7 +8,10 @@
 // followed by the sum over columns weighted by Au.  Every operand x is split as
 // x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), and each product is taken
 // as hi*hi + hi*lo + lo*hi (three MFMAs per block, FP32 accumulation): about 16
-// significant bits per operand, relative error of a few 1e-6.
+// significant bits per operand, relative error of a few 1e-6.  The F32 variants
+// (precision fp32_mfma) take FP32 operands with v_mfma_f32_16x16x4_f32 instead,
+// four samples (gridding) or four rows (degridding) per instruction: FP32
+// products and accumulation, relative error ~1e-7.
 //
 // A workgroup owns one tile of the plan (16 to 64 cells, sorted by the plan's
 // counting sort); each of its waves owns a region of one or two 16x16 subtiles
