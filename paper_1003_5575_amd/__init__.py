@@ -77,7 +77,13 @@ def make_params(n_grid, cell_lambda, support, oversample, n_chan, n_base, n_time
 
 class GridPlan:
     """A gridding plan over one cadence: uvw [B][T][3] (float64, metres, device),
-    freq_hz [C] (host sequence), weights [C][B][T] (float32, device; 0 = flagged)."""
+    freq_hz [C] (host sequence), weights [C][B][T] (float32, device; 0 = flagged).
+
+    precision: "fp32" (vector tile kernels, FP64 tile accumulation), "bf16x3"
+    (grid and degrid on the matrix cores with BF16 hi+lo operands) or "fp32_mfma"
+    (the same with FP32 operands); the matrix-core modes accept supports up to 24
+    and per-baseline kernels (set_baseline_kernels).  schedule: "auto", "tiles"
+    or "persistent" (launch of the FP32 tile kernels)."""
 
     def __init__(self, uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversample=8,
                  beta=None, conjugate=False, tile=0, stream=None, precision="fp32", schedule="auto"):
