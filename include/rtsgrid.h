@@ -65,17 +65,17 @@ typedef enum {
 typedef enum {
   RTS_PREC_FP32 = 0,    /* FP32 arithmetic, FP64 tile accumulation (all entry points) */
   RTS_PREC_BF16X3 = 1,  /* rts_grid and rts_degrid on the matrix cores (Eq. (1) and its adjoint
-                           per 16x16-cell tile): gridding is the contraction Av^T diag(wV) Au over
-                           the tile's samples, degridding H = Av G_tile followed by the k_x sum,
-                           with per-tile partial values added to the model with FP32 atomics.
-                           Operands are split into BF16 hi+lo (hi*hi + hi*lo + lo*hi, FP32
-                           accumulation; ~16 significant bits per operand; relative error a few
-                           1e-6).  The plan's tile (a multiple of 16 cells) is split into 16x16
-                           subtiles, one wave each.  The fused step of such a plan uses the FP32
-                           kernels. */
+                           per 16x16-cell subtile): gridding is the contraction Av^T diag(wV) Au
+                           over the subtile's samples, degridding H = Av G_subtile followed by the
+                           k_x sum, with per-region partial values added to the model with FP32
+                           atomics.  Operands are split into BF16 hi+lo (hi*hi + hi*lo + lo*hi,
+                           FP32 accumulation; ~16 significant bits per operand; relative error a
+                           few 1e-6).  The plan's tile (a multiple of 16 cells) is split into
+                           regions of one or two 16x16 subtiles, one wave each.  Supports up to
+                           24; per-baseline kernels (rts_plan_set_baseline_kernels).  The fused
+                           step of such a plan uses the FP32 tile kernels (support <= 16). */
   RTS_PREC_FP32_MFMA = 2  /* as RTS_PREC_BF16X3, with FP32 operands (v_mfma_f32_16x16x4_f32,
-                           FP32 accumulation): FP32 results on the matrix cores for wide
-                           kernels (supports up to 24, per-baseline kernels) */
+                           FP32 accumulation; relative error ~1e-7) */
 } rts_precision;
 
 typedef enum {
@@ -88,8 +88,8 @@ typedef enum {
 
 typedef struct {
   int32_t n_grid;       /* N: grid edge in cells, even, 16 <= N <= 8192                  */
-  int32_t support;      /* W: taps per axis, 2 <= W <= 16 (BF16x3 plans: <= 24; beyond 16
-                           only rts_grid and rts_degrid are available)                   */
+  int32_t support;      /* W: taps per axis, 2 <= W <= 16 (matrix-core plans: <= 24; beyond
+                           16 only rts_grid and rts_degrid are available)                */
   int32_t oversample;   /* OS: kernel phases per cell, 1 <= OS <= 64                     */
   int32_t n_chan;       /* C >= 1                                                         */
   int32_t n_base;       /* B >= 1                                                         */
@@ -98,7 +98,7 @@ typedef struct {
   double beta;          /* Kaiser-Bessel shape; <= 0 selects 2.34 * W                     */
   int32_t conjugate;    /* 1: also grid conj(w V) at (-u, -v) (rts_grid only)             */
   int32_t tile;         /* uv tile edge in cells: even, divides N, >= W+1, <= 64; 0 = choose
-                           (BF16x3 plans: also a multiple of 16)                          */
+                           (matrix-core plans: also a multiple of 16)                     */
   int32_t precision;    /* rts_precision                                                 */
   int32_t schedule;     /* rts_schedule: how the FP32 tile kernels are launched           */
 } rts_params;
@@ -232,7 +232,8 @@ rts_status rts_polconvert(const float *A, const float *P, float *S, int64_t n_pi
 
 /* Per-visibility kernels (Section 3: the gridder's kernel is fixed by the
  * calibration of the two tiles of each visibility's baseline; Table 4 uses a
- * 24 x 24 kernel).  After this call rts_grid and rts_degrid of a BF16x3 plan use,
+ * 24 x 24 kernel).  After this call rts_grid and rts_degrid of a matrix-core plan
+ * (RTS_PREC_BF16X3 or RTS_PREC_FP32_MFMA) use,
  * for every sample of baseline b, the separable kernel of that baseline instead
  * of the shared Kaiser-Bessel window:
  *     grid[c][cy+t_v][cx+t_u] += w V tab[b][r_y][t_v] tab[b][r_x][t_u],
@@ -244,7 +245,7 @@ rts_status rts_polconvert(const float *A, const float *P, float *S, int64_t n_pi
  * frees them and restores the shared kernel.  rts_grid_degrid and cadence graphs
  * keep the shared kernel and return RTS_E_UNSUPPORTED while per-baseline kernels
  * are set.
- * Errors: RTS_E_UNSUPPORTED (not a BF16x3 plan), RTS_E_INVALID, RTS_E_NOMEM,
+ * Errors: RTS_E_UNSUPPORTED (not a matrix-core plan), RTS_E_INVALID, RTS_E_NOMEM,
  * RTS_E_HIP. */
 rts_status rts_plan_set_baseline_kernels(rts_plan_t plan, const float *tab, void *stream);
 
