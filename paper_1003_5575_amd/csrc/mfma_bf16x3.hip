@@ -495,6 +495,22 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
 
+    // Column weights of the samples 4g + r whose H rows this lane receives.  From
+    // device memory (per-baseline tables) they are loaded before the contraction
+    // so that the loads overlap it; from LDS, after it (fewer live registers).
+    float kxv[4][DC];
+    uint32_t vis_r[4];
+    auto column_weights = [&]() {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint4 sl = ds[4 * g + r];
+#pragma unroll
+        for (int cb = 0; cb < DC; ++cb)
+          kxv[r][cb] = PB ? pb.tab[sl.y + i16 + kMT * cb] : lds_f32(lds, sl.y + 4u * i16 + 4u * kMT * cb);
+        vis_r[r] = sl.z;
+      }
+    };
+    if (PB) column_weights();
     f4_t hr[DC], hi[DC];
     if constexpr (F32) {
       // FP32: K step t covers region rows 4t + g; A[s][g] = k_y of sample s = i16.
@@ -549,19 +565,16 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     // columns of a lane row by halving exchanges (mirror, half mirror, xor 2,
     // xor 1): afterwards lane x holds the sum of value 4 b3 + 2 b2 + b1 (bits of
     // x), i.e. sample 4g + 2 b3 + b2, part b1.
+    if (!PB) column_weights();
     float v[8];
-    uint32_t vis_r[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const uint4 sl = ds[4 * g + r];
       v[2 * r] = v[2 * r + 1] = 0.0f;
 #pragma unroll
       for (int cb = 0; cb < DC; ++cb) {
-        const float kx = PB ? pb.tab[sl.y + i16 + kMT * cb] : lds_f32(lds, sl.y + 4u * i16 + 4u * kMT * cb);
-        v[2 * r] += hr[cb][r] * kx;
-        v[2 * r + 1] += hi[cb][r] * kx;
+        v[2 * r] += hr[cb][r] * kxv[r][cb];
+        v[2 * r + 1] += hi[cb][r] * kxv[r][cb];
       }
-      vis_r[r] = sl.z;
     }
     float u[4];
 #pragma unroll
