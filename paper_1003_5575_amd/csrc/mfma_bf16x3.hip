@@ -496,8 +496,9 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
 
     // Column weights of the samples 4g + r whose H rows this lane receives.  From
-    // device memory (per-baseline tables) they are loaded before the contraction
-    // so that the loads overlap it; from LDS, after it (fewer live registers).
+    // device memory (per-baseline tables), or ahead of the longer FP32-operand
+    // contraction, they are read before it so that the reads overlap it; for the
+    // BF16x3 contraction from LDS, after it (fewer live registers).
     float kxv[4][DC];
     uint32_t vis_r[4];
     auto column_weights = [&]() {
@@ -510,7 +511,7 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
         vis_r[r] = sl.z;
       }
     };
-    if (PB) column_weights();
+    if (PB || F32) column_weights();
     f4_t hr[DC], hi[DC];
     if constexpr (F32) {
       // FP32: K step t covers region rows 4t + g; A[s][g] = k_y of sample s = i16.
@@ -565,7 +566,7 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     // columns of a lane row by halving exchanges (mirror, half mirror, xor 2,
     // xor 1): afterwards lane x holds the sum of value 4 b3 + 2 b2 + b1 (bits of
     // x), i.e. sample 4g + 2 b3 + b2, part b1.
-    if (!PB) column_weights();
+    if (!PB && !F32) column_weights();
     float v[8];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
