@@ -1,5 +1,6 @@
 // Gridding and degridding as dense per-tile contractions on the matrix cores,
-// with BF16 hi+lo split operands and FP32 accumulation.
+// with BF16 hi+lo split operands (or FP32 operands) and FP32 accumulation.  The
+// kernel names keep the bf16x3 suffix for both operand types.
 //
 // For one 16x16-cell subtile of one channel, Eq. (1) restricted to the subtile is
 //     G_re = Av^T diag(w Re V) Au,   G_im = Av^T diag(w Im V) Au,
