@@ -63,8 +63,9 @@ class Chi2Fn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, V, w, G, plan):
         model, g_out, chi2 = plan.grid_degrid(V.contiguous(), w.contiguous(), G.contiguous())
-        valid = plan.valid_mask()
-        r = torch.where(valid, V - model, torch.zeros((), dtype=V.dtype, device=V.device))
+        # residual in place of the model (a buffer of this call): V - M, 0 where invalid
+        r = torch.sub(V, model, out=model)
+        r.masked_fill_(~plan.valid_mask(), 0)
         ctx.save_for_backward(r, w, g_out)
         return chi2
 
@@ -76,9 +77,9 @@ class Chi2Fn(torch.autograd.Function):
         if ctx.needs_input_grad[0]:
             gV = (2.0 * g32) * w * r
         if ctx.needs_input_grad[1]:
-            gw = g32 * (r.real * r.real + r.imag * r.imag)
+            gw = torch.view_as_real(r).square().sum(-1).mul_(g32)
         if ctx.needs_input_grad[2]:
-            gG = (-2.0 * g32) * g_out
+            gG = g_out * (-2.0 * g32)
         return gV, gw, gG, None
 
 
