@@ -423,7 +423,23 @@ def bench_mixed(args, torch, rts, make_workload):
         parts = [float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)])) for i in range(3)]
         return ms, parts
 
+    chi2 = torch.empty((), dtype=torch.float64, device=dev)
+
+    def timed_fused(p, K):
+        """The fused residual step alone (degrid, grid w (V - M), chi2) on the same inputs."""
+        for _ in range(args.warmup):
+            p.grid_degrid(vis, w, gin, model_out=model, grid_out=gout, chi2_out=chi2)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        ev[0].record(stream)
+        for k in range(K):
+            p.grid_degrid(vis, w, gin, model_out=model, grid_out=gout, chi2_out=chi2)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(K)]))
+
     K = args.steps
+    fused_ms = timed_fused(plan, K)
     ms, (plan_ms, g_ms, d_ms) = timed(plan, K)
     # per-channel error of the BF16x3 results on sampled channels
     errs = None
@@ -445,10 +461,12 @@ def bench_mixed(args, torch, rts, make_workload):
     plan.close()
     plan32 = rts.GridPlan(uvw, wl.freq_hz, w, N, wl.cell_lambda, support=W, oversample=OS)
     ms32, (p32, g32, d32) = timed(plan32, K)
+    fused32 = timed_fused(plan32, K)
     tile32 = plan32.info["tile"]
     plan32.close()
     # FP32 operands on the matrix cores, same inputs; error on the same channels
     planm = rts.GridPlan(uvw, wl.freq_hz, w, N, wl.cell_lambda, support=W, oversample=OS, precision="fp32_mfma")
+    fusedm = timed_fused(planm, K)
     msm, (pm, gm, dm) = timed(planm, K)
     planm.close()
     errs_m = None
@@ -468,12 +486,13 @@ def bench_mixed(args, torch, rts, make_workload):
                    "n_grid": N, "support": W, "oversample": OS, "tile": info["tile"],
                    "step": "plan update + BF16x3 grid + BF16x3 degrid, one launch each over all channels"},
         "breakdown": {"plan_ms": round(plan_ms, 4), "grid_ms": round(g_ms, 4), "degrid_ms": round(d_ms, 4),
-                      "n_listings": nl, "seg_max": info["seg_max"]},
+                      "fused_step_ms": round(fused_ms, 4), "n_listings": nl, "seg_max": info["seg_max"]},
         "fp32_path": {"ms_per_step": round(ms32, 4), "value": round(n_valid / ms32 / 1e3, 1), "tile": tile32,
-                      "plan_ms": round(p32, 4), "grid_ms": round(g32, 4), "degrid_ms": round(d32, 4)},
+                      "plan_ms": round(p32, 4), "grid_ms": round(g32, 4), "degrid_ms": round(d32, 4),
+                      "fused_step_ms": round(fused32, 4)},
         "fp32_mfma_path": {"ms_per_step": round(msm, 4), "value": round(n_valid / msm / 1e3, 1),
                            "plan_ms": round(pm, 4), "grid_ms": round(gm, 4), "degrid_ms": round(dm, 4),
-                           "error": errs_m},
+                           "fused_step_ms": round(fusedm, 4), "error": errs_m},
         "bf16x3_error": errs,
     }
     print(json.dumps(out), flush=True)
@@ -529,7 +548,23 @@ def bench_pervis(args, torch, rts, make_workload):
         ms = (time.perf_counter() - t0) / K * 1e3
         return ms, [float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)])) for i in range(3)]
 
+    chi2 = torch.empty((), dtype=torch.float64, device=dev)
+
+    def timed_fused(K):
+        """The fused residual step alone (degrid, grid w (V - M), chi2) with the plan's kernels."""
+        for _ in range(args.warmup):
+            plan.grid_degrid(vis, w, gin, model_out=model, grid_out=gout, chi2_out=chi2)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        ev[0].record(stream)
+        for k in range(K):
+            plan.grid_degrid(vis, w, gin, model_out=model, grid_out=gout, chi2_out=chi2)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[k].elapsed_time(ev[k + 1]) for k in range(K)]))
+
     K = args.steps
+    fused_ms = timed_fused(K)
     ms, (plan_ms, g_ms, d_ms) = timed(K)
     plan.set_baseline_kernels(None)
     ms_sh, (_, g_sh, d_sh) = timed(K)
@@ -538,6 +573,7 @@ def bench_pervis(args, torch, rts, make_workload):
     plan = rts.GridPlan(uvw, wl.freq_hz, w, N, wl.cell_lambda, support=W, oversample=OS, precision="fp32_mfma")
     plan.set_baseline_kernels(tab)
     ms_m, (_, g_m, d_m) = timed(K)
+    fused_m = timed_fused(K)
     plan.close()
     # algorithmic bytes of grid + degrid: visibilities and weights read and model
     # written (20 B per valid sample), the grids written, the touched cells read,
@@ -580,9 +616,11 @@ def bench_pervis(args, torch, rts, make_workload):
                    "support": W, "oversample": OS, "tile": info["tile"],
                    "step": "plan update + BF16x3 grid + BF16x3 degrid with per-baseline kernels"},
         "breakdown": {"plan_ms": round(plan_ms, 4), "grid_ms": round(g_ms, 4), "degrid_ms": round(d_ms, 4),
-                      "n_listings": info["n_listings"], "seg_max": info["seg_max"]},
+                      "fused_step_ms": round(fused_ms, 4), "n_listings": info["n_listings"],
+                      "seg_max": info["seg_max"]},
         "shared_kernel": {"ms_per_step": round(ms_sh, 4), "grid_ms": round(g_sh, 4), "degrid_ms": round(d_sh, 4)},
-        "fp32_mfma": {"ms_per_step": round(ms_m, 4), "grid_ms": round(g_m, 4), "degrid_ms": round(d_m, 4)},
+        "fp32_mfma": {"ms_per_step": round(ms_m, 4), "grid_ms": round(g_m, 4), "degrid_ms": round(d_m, 4),
+                      "fused_step_ms": round(fused_m, 4)},
         "roofline": {"bound": "hbm", "achieved": round(alg / kms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(alg / kms / 1e6 / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_grid_mfma_bf16x3<2, true> + k_degrid_mfma_bf16x3<2, true>",

@@ -73,7 +73,7 @@ typedef enum {
                            few 1e-6).  The plan's tile (a multiple of 16 cells) is split into
                            regions of one or two 16x16 subtiles, one wave each.  Supports up to
                            24; per-baseline kernels (rts_plan_set_baseline_kernels).  The fused
-                           step of such a plan uses the FP32 tile kernels (support <= 16). */
+                           step runs the same two kernels (degrid, then grid of w (V - M)). */
   RTS_PREC_FP32_MFMA = 2  /* as RTS_PREC_BF16X3, with FP32 operands (v_mfma_f32_16x16x4_f32,
                            FP32 accumulation; relative error ~1e-7) */
 } rts_precision;
@@ -149,8 +149,13 @@ rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *
 
 /* Fused residual step: M = degrid(grid_in); r = V - M (0 where invalid);
  * grid_out = grid(r, w); chi2 = sum_i w_i |r_i|^2 (FP64).  model_out (C*B*T
- * complex64) and chi2_out (one double in device memory) may be NULL.  grid_in and
- * grid_out must not overlap.  Plans built with conjugate=1 return RTS_E_UNSUPPORTED. */
+ * complex64) and chi2_out (one double in device memory) may be NULL, except that
+ * matrix-core plans need model_out (RTS_E_INVALID otherwise).  grid_in and
+ * grid_out must not overlap.  FP32 plans run one tile kernel (support <= 16 and
+ * the shared kernel only, else RTS_E_UNSUPPORTED); matrix-core plans run their
+ * degridding into model_out, then their gridding of w (V - M), then a chi2
+ * reduction, with supports up to 24 and per-baseline kernels.  Plans built with
+ * conjugate=1 return RTS_E_UNSUPPORTED. */
 rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weights,
                            const float *grid_in, float *model_out, float *grid_out,
                            double *chi2_out, void *stream);
@@ -163,7 +168,8 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
  * All buffers must stay allocated at the same addresses while the graph lives;
  * the capture contains no allocation, memset or host synchronisation.  The
  * work-list capacity limit of rts_plan_update applies (rts_plan_info.n_dropped).
- * Plans with conjugate copies return RTS_E_UNSUPPORTED. */
+ * The limits of rts_grid_degrid apply: matrix-core plans need model_out; plans
+ * with conjugate copies return RTS_E_UNSUPPORTED. */
 rts_status rts_cadence_graph_create(rts_graph_t *out, rts_plan_t plan, const double *uvw_m,
                                     const float *vis, const float *weights, const float *grid_in,
                                     float *model_out, float *grid_out, double *chi2_out, void *stream);
@@ -242,9 +248,11 @@ rts_status rts_polconvert(const float *A, const float *P, float *S, int64_t n_pi
  * copies use their baseline's table at their own phases).  The values are copied
  * into plan-owned padded tables (about 8*B*2*OS*(W+32) bytes, allocated on the
  * first call); tab may be freed once the stream has passed this call.  A NULL tab
- * frees them and restores the shared kernel.  rts_grid_degrid and cadence graphs
- * keep the shared kernel and return RTS_E_UNSUPPORTED while per-baseline kernels
- * are set.
+ * frees them and restores the shared kernel.  rts_grid, rts_degrid,
+ * rts_grid_degrid and cadence graphs of the plan all use them while set.  New
+ * tables replace the old ones at the same address (a live cadence graph replays
+ * with them); adding or removing tables while a cadence graph of the plan is
+ * alive returns RTS_E_INVALID.
  * Errors: RTS_E_UNSUPPORTED (not a matrix-core plan), RTS_E_INVALID, RTS_E_NOMEM,
  * RTS_E_HIP. */
 rts_status rts_plan_set_baseline_kernels(rts_plan_t plan, const float *tab, void *stream);
@@ -257,7 +265,8 @@ rts_status rts_plan_get_table(rts_plan_t plan, float *tab, int64_t capacity);
 
 rts_status rts_plan_get_info(rts_plan_t plan, rts_plan_info *info);
 
-/* Release the plan and its workspace (waits for the device). NULL is accepted. */
+/* Release the plan and its workspace (waits for the device). NULL is accepted.
+ * RTS_E_INVALID (nothing released) while a cadence graph of the plan is alive. */
 rts_status rts_plan_destroy(rts_plan_t plan);
 
 /* Message of the last failed call on this thread ("" if none). */

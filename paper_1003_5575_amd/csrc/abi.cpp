@@ -35,6 +35,12 @@ double bessel_i0(double x) {
   return sum;
 }
 
+// The matrix-core fused step (mfma_bf16x3.hip).
+hipError_t launch_grid_resid_mfma(const Plan &P, const TileArgs &a, hipStream_t s);
+hipError_t launch_chi2_mfma(const Plan &P, const TileArgs &a, double *out, hipStream_t s);
+// Cadence graphs captured from a plan and not yet destroyed (runtime.cpp).
+int live_graphs(const Plan *p);
+
 namespace {
 
 #define RTS_HIP(expr)                                                                   \
@@ -79,7 +85,7 @@ float bf16_value(uint16_t b) {
   return f;
 }
 
-// Plans whose rts_grid / rts_degrid run the matrix-core kernels.
+// Plans whose rts_grid / rts_degrid (and fused step) run the matrix-core kernels.
 bool mfma_precision(int p) { return p == RTS_PREC_BF16X3 || p == RTS_PREC_FP32_MFMA; }
 
 rts_status validate(const rts_params *p) {
@@ -542,8 +548,8 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
     set_error("rts_grid_degrid does not support plans built with conjugate=1");
     return RTS_E_UNSUPPORTED;
   }
-  if (plan->W > kMaxW || plan->d_pb_thl) {
-    set_error("the fused step runs the FP32 tile kernels: support <= %d and the shared kernel only", kMaxW);
+  if (!mfma_precision(plan->precision) && (plan->W > kMaxW || plan->d_pb_thl)) {
+    set_error("the fused step of an FP32 plan needs support <= %d and the shared kernel", kMaxW);
     return RTS_E_UNSUPPORTED;
   }
   RTS_REQUIRE(vis && weights && grid_in && grid_out, "vis, weights, grid_in, grid_out must be non-NULL");
@@ -562,6 +568,14 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
   a.write_model = model_out != nullptr;
   a.vec = vector_ok(*plan, vis, weights, model_out);
   hipStream_t s = (hipStream_t)stream;
+  if (mfma_precision(plan->precision)) {
+    // matrix-core plans: degrid into model_out, grid w (V - M), then chi2
+    RTS_REQUIRE(model_out != nullptr, "the fused step of a matrix-core plan needs model_out");
+    RTS_HIP(launch_degrid_mfma(*plan, a, s));
+    RTS_HIP(launch_grid_resid_mfma(*plan, a, s));
+    if (chi2_out) RTS_HIP(launch_chi2_mfma(*plan, a, chi2_out, s));
+    return RTS_OK;
+  }
   RTS_HIP(launch_tile(kFused, *plan, a, s));
   if (chi2_out) RTS_HIP(launch_chi2_reduce(plan->d_chi2_part, plan->nkeys, chi2_out, s));
   return RTS_OK;
@@ -600,6 +614,12 @@ rts_status rts_plan_set_baseline_kernels(rts_plan_t plan, const float *tab, void
   if (!mfma_precision(plan->precision)) {
     set_error("per-baseline kernels need a matrix-core plan (BF16x3 or FP32 on the matrix cores)");
     return RTS_E_UNSUPPORTED;
+  }
+  // replacing the tables keeps their addresses; adding or removing them would
+  // leave a captured graph with the wrong kernels or freed memory
+  if ((!tab || !plan->d_pb_thl) && live_graphs(plan)) {
+    set_error("destroy this plan's cadence graphs before adding or removing per-baseline kernels");
+    return RTS_E_INVALID;
   }
   if (!tab) {
     hipFree(plan->d_pb_thl);
@@ -657,6 +677,10 @@ rts_status rts_plan_get_info(rts_plan_t plan, rts_plan_info *info) {
 
 rts_status rts_plan_destroy(rts_plan_t plan) {
   if (!plan) return RTS_OK;
+  if (live_graphs(plan)) {
+    set_error("destroy this plan's cadence graphs before the plan");
+    return RTS_E_INVALID;
+  }
   hipError_t e = hipDeviceSynchronize();
   free_plan(plan);
   RTS_HIP(e);

@@ -227,7 +227,7 @@ __device__ __forceinline__ void slot_offsets_pb(const TileArgs &a, const PbTable
 // by the GR row blocks.  One v_mfma_f32_16x16x32_bf16 per term and block: K
 // runs over 32 sample slots.  Registers are capped at 80 so that three
 // workgroups of 8 waves share a CU.
-template <int GR, bool PB, bool F32>
+template <int GR, bool PB, bool F32, bool RES>
 __global__ __launch_bounds__(64 * max_waves<GR>()) __attribute__((amdgpu_waves_per_eu(6)))
 void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_lo, PbTables pb) {
   constexpr int kChunk = 32;                         // sample slots per MFMA K step
@@ -276,7 +276,12 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
           const size_t vi = rec.x + j;
           const size_t ci = vi + (size_t)(c * (a.ncopy - 1) + copy) * copy_stride;
           const uint16_t cw = a.coords[ci];
-          const float2 v = a.vis[vi];
+          float2 v = a.vis[vi];
+          if (RES) {                                 // the fused step grids w (V - M)
+            const float2 m = a.model[vi];
+            v.x -= m.x;
+            v.y -= m.y;
+          }
           const float wt = a.w[vi];
           uint32_t ya, xa;
           if (PB)
@@ -669,8 +674,15 @@ static unsigned mfma_grid_size(const Plan &P, const TileArgs &a) {
 template <int NR, bool PB, bool F32>
 void launch_grid_variant(const Plan &P, const TileArgs &a, hipStream_t s, const PbTables &pb, unsigned threads,
                          size_t lds) {
-  hipLaunchKernelGGL((k_grid_mfma_bf16x3<NR, PB, F32>), dim3(mfma_grid_size(P, a)), dim3(threads), lds, s, a,
-                     P.d_tab_hi, P.d_tab_lo, pb);
+  hipLaunchKernelGGL((k_grid_mfma_bf16x3<NR, PB, F32, false>), dim3(mfma_grid_size(P, a)), dim3(threads), lds,
+                     s, a, P.d_tab_hi, P.d_tab_lo, pb);
+}
+
+template <int NR, bool PB, bool F32>
+void launch_resid_variant(const Plan &P, const TileArgs &a, hipStream_t s, const PbTables &pb, unsigned threads,
+                          size_t lds) {
+  hipLaunchKernelGGL((k_grid_mfma_bf16x3<NR, PB, F32, true>), dim3(mfma_grid_size(P, a)), dim3(threads), lds,
+                     s, a, P.d_tab_hi, P.d_tab_lo, pb);
 }
 
 template <int NR, bool PB, bool F32>
@@ -718,6 +730,51 @@ hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   const PbTables pb = pb_tables(P);
   RTS_MFMA_PICK(launch_degrid_variant);
   return hipGetLastError();
+}
+
+// The fused step's gridding pass: w (V - M) over the valid samples, M the model
+// written by launch_degrid_mfma into a.model.
+hipError_t launch_grid_resid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
+  const int pair = P.tile % (2 * kMT) == 0 ? 2 : 1;
+  const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT) / pair);
+  const bool pbk = P.d_pb_thl != nullptr, f32 = P.precision == RTS_PREC_FP32_MFMA;
+  const size_t lds = pbk ? 0 : padded_lds_bytes(a, pair * kMT, kMT);
+  const PbTables pb = pb_tables(P);
+  RTS_MFMA_PICK(launch_resid_variant);
+  return hipGetLastError();
+}
+
+namespace {
+// chi2 = sum over valid samples of w |V - M|^2: FP64 partial sums per workgroup
+// (grid-stride over the samples, at most `parts` workgroups).  Validity is read
+// from the +uv copy's coordinates: coords is [C][ncopy][B][T], samples [C][B][T].
+__global__ __launch_bounds__(256) void k_chi2_samples(const float2 *__restrict__ vis, const float2 *__restrict__ model,
+                                                      const float *__restrict__ w, const uint16_t *__restrict__ coords,
+                                                      int64_t n, int64_t bt, int extra, double *part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float2 v = vis[i], m = model[i];
+    const float rr = v.x - m.x, ri = v.y - m.y;
+    const float c2 = w[i] * fmaf(rr, rr, ri * ri);
+    acc += (coords[i + (i / bt) * extra * bt] & kCoordValid) ? (double)c2 : 0.0;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+}  // namespace
+
+// The fused step's chi-squared over the valid samples.
+hipError_t launch_chi2_mfma(const Plan &P, const TileArgs &a, double *out, hipStream_t s) {
+  const int64_t n = (int64_t)P.C * P.B * P.T;
+  const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(P.nkeys, (n + 2047) / 2048));
+  hipLaunchKernelGGL(k_chi2_samples, dim3((unsigned)parts), dim3(256), 0, s, a.vis, a.model, a.w, a.coords, n,
+                     (int64_t)P.B * P.T, P.ncopy - 1, P.d_chi2_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_chi2_reduce(P.d_chi2_part, parts, out, s);
 }
 
 }  // namespace rts

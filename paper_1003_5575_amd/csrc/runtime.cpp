@@ -33,7 +33,19 @@ using TuneKey = std::tuple<int, int, int, int, int, int, int, long long>;
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune_cache;
 
+// Live cadence graphs per plan: a graph holds the plan's buffer addresses.
+std::mutex g_graph_mu;
+std::map<const Plan *, int> g_graph_count;
+
 }  // namespace
+
+namespace rts {
+int live_graphs(const Plan *p) {
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  const auto it = g_graph_count.find(p);
+  return it == g_graph_count.end() ? 0 : it->second;
+}
+}  // namespace rts
 
 extern "C" {
 
@@ -49,9 +61,14 @@ rts_status rts_cadence_graph_create(rts_graph_t *out, rts_plan_t plan, const dou
     set_error("cadence graphs need a plan without conjugate copies");
     return RTS_E_UNSUPPORTED;
   }
-  if (plan->W > kMaxW || plan->d_pb_thl) {
-    set_error("cadence graphs run the FP32 fused step: support <= %d and the shared kernel only", kMaxW);
+  const bool mfma_plan = plan->precision == RTS_PREC_BF16X3 || plan->precision == RTS_PREC_FP32_MFMA;
+  if (!mfma_plan && (plan->W > kMaxW || plan->d_pb_thl)) {
+    set_error("cadence graphs of FP32 plans need support <= %d and the shared kernel", kMaxW);
     return RTS_E_UNSUPPORTED;
+  }
+  if (mfma_plan && !model_out) {
+    set_error("cadence graphs of matrix-core plans need model_out");
+    return RTS_E_INVALID;
   }
   hipStream_t cs = nullptr;
   RTS_HIP_R(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -90,6 +107,10 @@ rts_status rts_cadence_graph_create(rts_graph_t *out, rts_plan_t plan, const dou
   g->graph = graph;
   g->exec = exec;
   g->plan = plan;
+  {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    ++g_graph_count[plan];
+  }
   *out = g;
   return RTS_OK;
 }
@@ -106,6 +127,11 @@ rts_status rts_cadence_graph_launch(rts_graph_t graph, void *stream) {
 
 rts_status rts_cadence_graph_destroy(rts_graph_t graph) {
   if (!graph) return RTS_OK;
+  {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    const auto it = g_graph_count.find(graph->plan);
+    if (it != g_graph_count.end() && --it->second <= 0) g_graph_count.erase(it);
+  }
   hipGraphExecDestroy(graph->exec);
   hipGraphDestroy(graph->graph);
   delete graph;

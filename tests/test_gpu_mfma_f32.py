@@ -54,8 +54,8 @@ def test_fp32_mfma_matches_oracle(rts, W, OS, N, tile, conj, per_baseline):
     assert max(ge) <= RTOL_L2 and max(me) <= RTOL_L2
 
 
-def test_fp32_mfma_fused_step_uses_the_tile_kernels(rts):
-    """The fused step of an fp32_mfma plan (W <= 16) runs the FP32 tile kernels."""
+def test_fp32_mfma_fused_step_with_an_empty_model(rts):
+    """The fused step of an fp32_mfma plan with G_in = 0 grids the visibilities."""
     wl, freq, du = small_case(n_ant=40, channels=(3, 29), N=256, W=7, OS=8, weights="uniform")
     uvw, vis, w = to_dev(torch, wl)
     plan = rts.GridPlan(uvw, freq, w, 256, du, precision="fp32_mfma")
