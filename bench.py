@@ -623,7 +623,7 @@ def bench_pervis(args, torch, rts, make_workload):
                       "fused_step_ms": round(fused_m, 4)},
         "roofline": {"bound": "hbm", "achieved": round(alg / kms / 1e6, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(alg / kms / 1e6 / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_grid_mfma_bf16x3<2, true> + k_degrid_mfma_bf16x3<2, true>",
+                     "kernel": "k_grid_mfma_bf16x3<2, true, false, false> + k_degrid_mfma_bf16x3<2, true, false>",
                      "kernel_ms": round(kms, 4), "alg_bytes_per_launch": int(alg), "touched_cells": int(touched)},
         "cpu_baseline": cpu,
         "bf16x3_error": errs,
