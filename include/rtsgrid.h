@@ -59,7 +59,7 @@ typedef enum {
   RTS_E_INVALID = 1,      /* bad argument (null pointer, size out of range, ...) */
   RTS_E_NOMEM = 2,        /* device or host allocation failed */
   RTS_E_HIP = 3,          /* a HIP runtime call failed */
-  RTS_E_UNSUPPORTED = 4,  /* valid request this build does not implement */
+  RTS_E_UNSUPPORTED = 4,  /* valid request the library does not implement */
 } rts_status;
 
 typedef enum {
