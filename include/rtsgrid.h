@@ -151,7 +151,7 @@ rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *
  * grid_out = grid(r, w); chi2 = sum_i w_i |r_i|^2 (FP64).  model_out (C*B*T
  * complex64) and chi2_out (one double in device memory) may be NULL, except that
  * matrix-core plans need model_out (RTS_E_INVALID otherwise).  grid_in and
- * grid_out must not overlap.  FP32 plans run one tile kernel (support <= 16 and
+ * grid_out must not overlap, nor model_out any other buffer (RTS_E_INVALID).  FP32 plans run one tile kernel (support <= 16 and
  * the shared kernel only, else RTS_E_UNSUPPORTED); matrix-core plans run their
  * degridding into model_out, then their gridding of w (V - M), then a chi2
  * reduction, with supports up to 24 and per-baseline kernels.  Plans built with

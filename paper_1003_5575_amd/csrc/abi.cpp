@@ -559,6 +559,17 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
   const size_t gbytes = (size_t)plan->C * plan->N * plan->N * 8;
   const char *gi = (const char *)grid_in, *go = (const char *)grid_out;
   RTS_REQUIRE(gi + gbytes <= go || go + gbytes <= gi, "grid_in and grid_out overlap");
+  if (model_out) {
+    // the model is written while the visibilities, weights and G_in are still read
+    const size_t n = (size_t)plan->C * plan->B * plan->T;
+    const char *m = (const char *)model_out;
+    auto apart = [&](const void *p, size_t bytes) {
+      const char *q = (const char *)p;
+      return m + 8 * n <= q || q + bytes <= m;
+    };
+    RTS_REQUIRE(apart(vis, 8 * n) && apart(weights, 4 * n) && apart(grid_in, gbytes) && apart(grid_out, gbytes),
+                "model_out overlaps vis, weights, grid_in or grid_out");
+  }
   TileArgs a = tile_args(*plan);
   a.vis = (const float2 *)vis;
   a.w = weights;

@@ -194,3 +194,22 @@ def test_graph_lifetime_guards(rts):
     graph.close()
     plan.set_baseline_kernels(None)                               # no live graph: allowed
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_fused_step_refuses_a_model_that_aliases_an_input(rts, prec):
+    """model_out may not share memory with vis, weights or the grids (the model is
+    written while they are still read); the refusal leaves the outputs alone."""
+    wl, freq, du = small_case(seed=9, n_ant=40, channels=(0, 1), N=256)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, 256, du, precision=prec)
+    gin = torch.zeros((2, 256, 256), dtype=torch.complex64, device="cuda")
+    vis0 = vis.clone()
+    with pytest.raises(rts.RtsError):
+        plan.grid_degrid(vis, w, gin, model_out=vis)
+    assert torch.equal(vis, vis0)
+    gview = gin.view(-1)[:vis.numel()].view(vis.shape)
+    with pytest.raises(rts.RtsError):
+        plan.grid_degrid(vis, w, gin, model_out=gview)
+    m, g, c2 = plan.grid_degrid(vis, w, gin)              # distinct buffers: accepted
+    assert torch.count_nonzero(m) == 0
