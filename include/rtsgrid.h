@@ -12,8 +12,9 @@
  * is the adjoint without weights,
  *     M_i = sum_{x,y} k(y - y_i) k(x - x_i) G[c][y][x].
  * Coordinates: x_i = u_i f_c / (c du) + N/2 cells (pixel N/2 is u = 0), snapped to
- * 1/OS cell by rounding half up; this is the only FP64 arithmetic, everything
- * after it is FP32.  A sample is valid iff its weight (at plan time) is non-zero
+ * 1/OS cell by rounding half up; this is the only FP64 arithmetic besides the
+ * accumulators and chi-squared sums, the rest is FP32 (or the matrix-core forms
+ * of rts_precision).  A sample is valid iff its weight (at plan time) is non-zero
  * and every tap lies on the grid; invalid samples contribute nothing and predict 0.
  *
  * Layouts (row-major, C-contiguous):
@@ -39,7 +40,9 @@
  * enqueue asynchronously on it, except: rts_grid_plan synchronises it (once, to
  * size the work list); rts_plan_get_info waits for the last re-plan's counts;
  * the first rts_image call of a plan builds its FFT plan and correction table
- * (allocation and a synchronous copy); rts_autotune_tile times on the stream.
+ * (allocation and a synchronous copy); the first rts_plan_set_baseline_kernels
+ * call allocates the per-baseline tables; rts_autotune_tile times on the stream;
+ * rts_plan_destroy waits for the device.
  * One plan must not be used concurrently on two streams.
  */
 #ifndef RTSGRID_H
