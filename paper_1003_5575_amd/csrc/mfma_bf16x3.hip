@@ -261,6 +261,10 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
   uint2 *q = queue[wave];
   // seg_max (2, 4 or 8) sample slots per listing, kChunk / seg_max listings per chunk
   const int lg = __builtin_ctz((unsigned)a.seg_max);
+  // Residual form: this wave's share of chi2 = sum w |V - M|^2, each sample
+  // counted once, by the wave whose region holds its window origin in the home
+  // listing of its segment.
+  double chi2 = 0.0;
 
   for_subtile_chunks(a, beg, end, x0, y0, RW, RH, true, q, kChunk >> lg, [&](int n) {
     // Stage the chunk: slot lane holds sample (lane mod seg_max) of queued record lane / seg_max.
@@ -277,12 +281,17 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
           const size_t ci = vi + (size_t)(c * (a.ncopy - 1) + copy) * copy_stride;
           const uint16_t cw = a.coords[ci];
           float2 v = a.vis[vi];
+          const float wt = a.w[vi];
           if (RES) {                                 // the fused step grids w (V - M)
             const float2 m = a.model[vi];
             v.x -= m.x;
             v.y -= m.y;
+            const int dx0 = (int)(rec.y & kRecXMask) - x0;
+            const int dy0 = (int)((rec.y >> kRecYShift) & kRecXMask) - y0;
+            const bool mine = ((rec.y >> kRecHomeBit) & 1u) && copy == 0 && (unsigned)dx0 < (unsigned)RW &&
+                              (unsigned)dy0 < (unsigned)RH && (cw & kCoordValid);
+            if (mine) chi2 += (double)(wt * fmaf(v.x, v.x, v.y * v.y));
           }
-          const float wt = a.w[vi];
           uint32_t ya, xa;
           if (PB)
             slot_offsets_pb(a, pb, (uint32_t)vi, rec.y, cw, x0, y0, ya, xa);
@@ -377,6 +386,19 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
     }
     __builtin_amdgcn_wave_barrier();   // the next chunk's slot writes follow these reads
   });
+
+  if constexpr (RES) {
+    // one partial chi2 per workgroup (every key has exactly one workgroup)
+    __shared__ double red[max_waves<GR>()];
+    for (int o = 32; o > 0; o >>= 1) chi2 += __shfl_down(chi2, o, 64);
+    if (lane == 0) red[wave] = chi2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+      a.chi2_part[key] = t;
+    }
+  }
 
   // D[y][x] of row block rb sits in lane x + 16 * (y / 4), register y % 4.
   float2 *out = a.gout + ((size_t)c * a.N + y0) * a.N + x0;
@@ -744,37 +766,11 @@ hipError_t launch_grid_resid_mfma(const Plan &P, const TileArgs &a, hipStream_t 
   return hipGetLastError();
 }
 
-namespace {
-// chi2 = sum over valid samples of w |V - M|^2: FP64 partial sums per workgroup
-// (grid-stride over the samples, at most `parts` workgroups).  Validity is read
-// from the +uv copy's coordinates: coords is [C][ncopy][B][T], samples [C][B][T].
-__global__ __launch_bounds__(256) void k_chi2_samples(const float2 *__restrict__ vis, const float2 *__restrict__ model,
-                                                      const float *__restrict__ w, const uint16_t *__restrict__ coords,
-                                                      int64_t n, int64_t bt, int extra, double *part) {
-  __shared__ double red[4];
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const float2 v = vis[i], m = model[i];
-    const float rr = v.x - m.x, ri = v.y - m.y;
-    const float c2 = w[i] * fmaf(rr, rr, ri * ri);
-    acc += (coords[i + (i / bt) * extra * bt] & kCoordValid) ? (double)c2 : 0.0;
-  }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-}  // namespace
 
-// The fused step's chi-squared over the valid samples.
-hipError_t launch_chi2_mfma(const Plan &P, const TileArgs &a, double *out, hipStream_t s) {
-  const int64_t n = (int64_t)P.C * P.B * P.T;
-  const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(P.nkeys, (n + 2047) / 2048));
-  hipLaunchKernelGGL(k_chi2_samples, dim3((unsigned)parts), dim3(256), 0, s, a.vis, a.model, a.w, a.coords, n,
-                     (int64_t)P.B * P.T, P.ncopy - 1, P.d_chi2_part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_chi2_reduce(P.d_chi2_part, parts, out, s);
+// The fused step's chi-squared: the residual gridding launch left one partial
+// sum per key in P.d_chi2_part.
+hipError_t launch_chi2_mfma(const Plan &P, const TileArgs &, double *out, hipStream_t s) {
+  return launch_chi2_reduce(P.d_chi2_part, P.nkeys, out, s);
 }
 
 }  // namespace rts
