@@ -213,3 +213,24 @@ def test_fused_step_refuses_a_model_that_aliases_an_input(rts, prec):
         plan.grid_degrid(vis, w, gin, model_out=gview)
     m, g, c2 = plan.grid_degrid(vis, w, gin)              # distinct buffers: accepted
     assert torch.count_nonzero(m) == 0
+
+
+def test_mfma_maximum_sizes(rts):
+    """The largest grid and support of the matrix-core path (N = 8192, W = 24,
+    OS = 16, 16,384 tiles of 64 cells on one channel): gridding and the fused step
+    against the oracle."""
+    N, W, OS = 8192, 24, 16
+    wl, freq, du = small_case(seed=11, n_ant=40, channels=(17,), N=N, W=W, OS=OS, weights="uniform",
+                              flag_frac=0.1)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, precision="bf16x3")
+    assert plan.info["tile"] == 64
+    geom = O.Geometry(wl.uvw_m, freq, wl.weights, N, du, W, OS)
+    G = plan.grid(vis, w).cpu().numpy()
+    assert rel_l2(G[0], O.grid(geom, wl.vis, wl.weights)[0]) <= TOL["bf16x3"]
+    del G
+    rng = np.random.default_rng(3)
+    Gin = (0.1 * (rng.standard_normal((1, N, N)) + 1j * rng.standard_normal((1, N, N)))).astype(np.complex64)
+    m, g, c2 = plan.grid_degrid(vis, w, torch.from_numpy(Gin).cuda())
+    ref = O.grid_degrid(geom, wl.vis, wl.weights, Gin.astype(np.complex128))
+    check(m.cpu().numpy(), g.cpu().numpy(), c2.item(), ref, geom.valid, TOL["bf16x3"], "max sizes bf16x3")
