@@ -37,7 +37,6 @@ double bessel_i0(double x) {
 
 // The matrix-core fused step (mfma_bf16x3.hip).
 hipError_t launch_grid_resid_mfma(const Plan &P, const TileArgs &a, hipStream_t s);
-hipError_t launch_chi2_mfma(const Plan &P, const TileArgs &a, double *out, hipStream_t s);
 // Cadence graphs captured from a plan and not yet destroyed (runtime.cpp).
 int live_graphs(const Plan *p);
 
@@ -580,11 +579,12 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
   a.vec = vector_ok(*plan, vis, weights, model_out);
   hipStream_t s = (hipStream_t)stream;
   if (mfma_precision(plan->precision)) {
-    // matrix-core plans: degrid into model_out, grid w (V - M), then chi2
+    // matrix-core plans: degrid into model_out, then grid w (V - M), which also
+    // leaves the chi2 partial sums per key
     RTS_REQUIRE(model_out != nullptr, "the fused step of a matrix-core plan needs model_out");
     RTS_HIP(launch_degrid_mfma(*plan, a, s));
     RTS_HIP(launch_grid_resid_mfma(*plan, a, s));
-    if (chi2_out) RTS_HIP(launch_chi2_mfma(*plan, a, chi2_out, s));
+    if (chi2_out) RTS_HIP(launch_chi2_reduce(plan->d_chi2_part, plan->nkeys, chi2_out, s));
     return RTS_OK;
   }
   RTS_HIP(launch_tile(kFused, *plan, a, s));

@@ -755,7 +755,8 @@ hipError_t launch_degrid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
 }
 
 // The fused step's gridding pass: w (V - M) over the valid samples, M the model
-// written by launch_degrid_mfma into a.model.
+// written by launch_degrid_mfma into a.model; it also leaves one partial sum of
+// chi2 per key in a.chi2_part.
 hipError_t launch_grid_resid_mfma(const Plan &P, const TileArgs &a, hipStream_t s) {
   const int pair = P.tile % (2 * kMT) == 0 ? 2 : 1;
   const unsigned threads = 64u * (unsigned)((P.tile / kMT) * (P.tile / kMT) / pair);
@@ -766,11 +767,5 @@ hipError_t launch_grid_resid_mfma(const Plan &P, const TileArgs &a, hipStream_t 
   return hipGetLastError();
 }
 
-
-// The fused step's chi-squared: the residual gridding launch left one partial
-// sum per key in P.d_chi2_part.
-hipError_t launch_chi2_mfma(const Plan &P, const TileArgs &, double *out, hipStream_t s) {
-  return launch_chi2_reduce(P.d_chi2_part, P.nkeys, out, s);
-}
 
 }  // namespace rts
