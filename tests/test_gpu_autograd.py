@@ -116,3 +116,30 @@ def test_adjoint_identity_on_gpu(rts):
     rhs = torch.vdot(x.flatten().to(torch.complex128), (w * plan.degrid(y)).flatten().to(torch.complex128))
     scale = plan.grid(x, w).abs().pow(2).sum().sqrt().item() * y.abs().pow(2).sum().sqrt().item()
     assert abs((lhs - rhs).item()) <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("prec,W,OS,tol", [("fp32_mfma", 24, 8, RTOL_L2), ("bf16x3", 16, 16, 3e-5)])
+def test_chi2_gradients_through_matrix_core_plans(rts, prec, W, OS, tol):
+    """The chi-squared and its gradients with a matrix-core plan (its own fused
+    step: degridding, then the residual gridding) against the oracle.  dL/dG is a
+    gridding of the residual, so it carries the model's error as in the fused-step
+    bound (factor 1 + |M| / |r|, about 2 here)."""
+    N = 256
+    wl, freq, du = small_case(seed=6, n_ant=40, channels=(0, 17, 31), N=N, W=W, OS=OS, weights="uniform",
+                              flag_frac=0.1, offgrid_frac=0.02)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, precision=prec)
+    geom = O.Geometry(wl.uvw_m, freq, wl.weights, N, du, W, OS)
+    rng = np.random.default_rng(6)
+    G0 = (0.1 * (rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N)))).astype(np.complex64)
+    G = torch.from_numpy(G0).cuda().requires_grad_(True)
+    V = vis.clone().requires_grad_(True)
+    wt = w.clone().requires_grad_(True)
+    loss = rts.chi2(V, wt, G, plan)
+    loss.backward()
+    chi2, gG, gw, gV = O.chi2_gradients(geom, wl.vis, wl.weights, G0.astype(np.complex128))
+    assert abs(loss.item() - chi2) <= 4 * tol * chi2
+    for c in range(3):
+        assert rel_l2(G.grad[c].cpu().numpy(), gG[c]) <= 4 * tol
+        assert rel_l2(wt.grad[c].cpu().numpy(), gw[c]) <= 4 * tol
+        assert rel_l2(V.grad[c].cpu().numpy(), gV[c]) <= 4 * tol
