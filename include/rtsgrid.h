@@ -91,8 +91,7 @@ typedef enum {
 
 typedef struct {
   int32_t n_grid;       /* N: grid edge in cells, even, 16 <= N <= 8192                  */
-  int32_t support;      /* W: taps per axis, 2 <= W <= 16 (matrix-core plans: <= 24; beyond
-                           16 only rts_grid and rts_degrid are available)                */
+  int32_t support;      /* W: taps per axis, 2 <= W <= 16 (matrix-core plans: <= 24)      */
   int32_t oversample;   /* OS: kernel phases per cell, 1 <= OS <= 64                     */
   int32_t n_chan;       /* C >= 1                                                         */
   int32_t n_base;       /* B >= 1                                                         */
@@ -154,11 +153,11 @@ rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *
  * grid_out = grid(r, w); chi2 = sum_i w_i |r_i|^2 (FP64).  model_out (C*B*T
  * complex64) and chi2_out (one double in device memory) may be NULL, except that
  * matrix-core plans need model_out (RTS_E_INVALID otherwise).  grid_in and
- * grid_out must not overlap, nor model_out any other buffer (RTS_E_INVALID).  FP32 plans run one tile kernel (support <= 16 and
- * the shared kernel only, else RTS_E_UNSUPPORTED); matrix-core plans run their
- * degridding into model_out, then their gridding of w (V - M), then a chi2
- * reduction, with supports up to 24 and per-baseline kernels.  Plans built with
- * conjugate=1 return RTS_E_UNSUPPORTED. */
+ * grid_out must not overlap, nor may model_out overlap any other buffer
+ * (RTS_E_INVALID).  FP32 plans run one tile kernel; matrix-core plans run their
+ * degridding into model_out, then their gridding of w (V - M), which also forms
+ * the chi2 partial sums, then one reduction.  Plans built with conjugate=1 return
+ * RTS_E_UNSUPPORTED. */
 rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weights,
                            const float *grid_in, float *model_out, float *grid_out,
                            double *chi2_out, void *stream);
