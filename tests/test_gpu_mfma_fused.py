@@ -234,3 +234,40 @@ def test_mfma_maximum_sizes(rts):
     m, g, c2 = plan.grid_degrid(vis, w, torch.from_numpy(Gin).cuda())
     ref = O.grid_degrid(geom, wl.vis, wl.weights, Gin.astype(np.complex128))
     check(m.cpu().numpy(), g.cpu().numpy(), c2.item(), ref, geom.valid, TOL["bf16x3"], "max sizes bf16x3")
+
+
+@pytest.mark.parametrize("T", [1, 3, 5, 9, 16])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32_mfma"])
+def test_mfma_fused_step_ragged_time_axis(rts, T, prec):
+    """Track lengths below, between and above the per-segment sample limit, with
+    20% of the samples flagged, through the matrix-core fused step (W = 16)."""
+    from synth import mwa
+    from tests.gpu_helpers import fit_cell
+    W, OS, N = 16, 8, 256
+    cfg = mwa.Config("t%d" % T, 30, T, 3, 140e6, 10e6, N, W, OS, n_sources=2)
+    wl = mwa.make_workload(cfg, seed=T)
+    freq = wl.freq_hz
+    du = fit_cell(wl.uvw_m, freq, N, W)
+    rng = np.random.default_rng(T)
+    wl.weights = rng.uniform(0.5, 1.5, wl.weights.shape).astype(np.float32)
+    wl.weights[rng.random(wl.weights.shape) < 0.2] = 0
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, N, du, support=W, oversample=OS, tile=32, precision=prec)
+    geom = O.Geometry(wl.uvw_m, freq, wl.weights, N, du, W, OS)
+    Gin = (0.1 * (rng.standard_normal((3, N, N)) + 1j * rng.standard_normal((3, N, N)))).astype(np.complex64)
+    m, g, c2 = plan.grid_degrid(vis, w, torch.from_numpy(Gin).cuda())
+    ref = O.grid_degrid(geom, wl.vis, wl.weights, Gin.astype(np.complex128))
+    check(m.cpu().numpy(), g.cpu().numpy(), c2.item(), ref, geom.valid, TOL[prec], f"ragged T={T} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32_mfma"])
+def test_mfma_fused_step_everything_flagged(rts, prec):
+    """No valid sample: zero model, zero grid, chi2 exactly 0."""
+    wl, freq, du = small_case(seed=12, n_ant=20, channels=(0, 5), N=128, W=24, OS=8)
+    wl.weights[:] = 0
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, 128, du, support=24, oversample=8, precision=prec)
+    assert plan.info["n_valid"] == 0
+    gin = torch.ones((2, 128, 128), dtype=torch.complex64, device="cuda")
+    m, g, c2 = plan.grid_degrid(vis, w, gin)
+    assert torch.all(m == 0) and torch.all(g == 0) and c2.item() == 0.0
