@@ -162,6 +162,36 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
                            const float *grid_in, float *model_out, float *grid_out,
                            double *chi2_out, void *stream);
 
+/* Backward of gridding, for automatic differentiation of Eq. (1): with D the
+ * plan's degridding (the adjoint of its gridding without weights),
+ *     grad_vis     = w * D(grad_grid)                    (complex, [C][B][T])
+ *     grad_weights = Re(conj(vis) * D(grad_grid))         (float,   [C][B][T])
+ * in PyTorch's convention for complex gradients (dL/dRe + i dL/dIm); both are 0 at
+ * samples the plan does not grid.  grad_grid: complex64 [C][N][N], the gradient
+ * with respect to the plan's grid output.  grad_vis is required (it also holds
+ * D(grad_grid) while the weight term is formed); grad_weights may be NULL.  Device
+ * buffers, caller-owned; grad_vis and grad_weights must not overlap each other or
+ * the inputs.  Asynchronous on `stream`; allocates nothing.
+ * Errors: RTS_E_UNSUPPORTED for plans built with conjugate=1 (their gridding also
+ * adds conj(w V), which is not complex-linear in V), RTS_E_INVALID, RTS_E_HIP. */
+rts_status rts_grid_backward(rts_plan_t plan, const float *vis, const float *weights, const float *grad_grid,
+                             float *grad_vis, float *grad_weights, void *stream);
+
+/* Backward of the chi-squared of the fused step, chi2 = sum_i w_i |vis_i - model_i|^2
+ * over the plan's valid samples, with model = D(grid_in).  From the model and the
+ * grid the fused step wrote (grid_resid = D^T(w r), r = vis - model at valid
+ * samples, 0 elsewhere) and the upstream gradient g = dL/dchi2 (one double in
+ * device memory):
+ *     grad_vis = 2 g w r,   grad_weights = g |r|^2,   grad_grid = -2 g grid_resid
+ * (PyTorch's convention for complex gradients).  Each output may be NULL; buffers
+ * are device memory, caller-owned, outputs must not overlap the inputs
+ * (grad_grid may be grid_resid itself).  Asynchronous on `stream`; allocates nothing.
+ * Errors: RTS_E_UNSUPPORTED for plans built with conjugate=1, RTS_E_INVALID,
+ * RTS_E_HIP. */
+rts_status rts_chi2_backward(rts_plan_t plan, const float *vis, const float *weights, const float *model,
+                             const float *grid_resid, const double *grad_chi2, float *grad_vis,
+                             float *grad_weights, float *grad_grid, void *stream);
+
 /* One cadence step as a HIP graph: rts_plan_update(uvw_m, weights) followed by
  * rts_grid_degrid(vis, weights, grid_in -> model_out, grid_out, chi2_out) is
  * captured once (on a private stream, after the work already queued on `stream`)
@@ -237,6 +267,16 @@ rts_status rts_image(rts_plan_t plan, const float *grid, float *image_out, void 
  * pointers), RTS_E_HIP. */
 rts_status rts_polconvert(const float *A, const float *P, float *S, int64_t n_pix, int n_chan,
                           int64_t a_chan_stride, void *stream);
+
+/* Streaming device copy of `bytes` bytes from src to dst (device memory, not
+ * overlapping, both 16-byte aligned): each byte is read once and written once with
+ * 16-byte vector accesses, the bulk access pattern of the tile kernels.  It is the
+ * reference for the attainable HBM bandwidth that throughput figures are reported
+ * beside (not part of the method).  bytes == 0 is a no-op.  Asynchronous on
+ * `stream`; allocates nothing.
+ * Errors: RTS_E_INVALID (negative size, NULL, misaligned or overlapping buffers),
+ * RTS_E_HIP. */
+rts_status rts_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
 
 /* Per-visibility kernels (Section 3: the gridder's kernel is fixed by the
  * calibration of the two tiles of each visibility's baseline; Table 4 uses a

@@ -35,6 +35,7 @@ def load():
         lib.orc_degrid.argtypes = [I, I, I, P, P, P, I, D, I, I, P, P, P]
         lib.orc_grid_degrid.argtypes = [I, I, I, P, P, P, P, I, D, I, I, P, P, P, P, P]
         lib.orc_num_threads.restype = I
+        lib.orc_set_num_threads.argtypes = [I]
         _lib = lib
     return _lib
 
@@ -56,6 +57,11 @@ def _prep(uvw_m, freq_hz, vis, weights):
 
 def num_threads() -> int:
     return load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel channel loops (its OpenMP team size)."""
+    load().orc_set_num_threads(int(n))
 
 
 def grid(uvw_m, freq_hz, vis, weights, N, du, W=7, OS=8, beta=None, conjugate=False):

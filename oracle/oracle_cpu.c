@@ -179,3 +179,7 @@ int orc_num_threads(void) {
   }
   return n;
 }
+
+/* Thread count of the parallel loops above (the timed CPU baseline runs once on
+ * every host core and once on a single core). */
+void orc_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

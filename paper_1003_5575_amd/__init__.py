@@ -16,7 +16,7 @@ import ctypes
 from . import _lib
 from ._lib import RtsError, RtsParams, RtsPlanInfo  # noqa: F401
 
-__all__ = ["GridPlan", "CadenceGraph", "autotune_tile", "compute_coords", "polconvert", "RtsError", "library_path", "version", "GridFn", "DegridFn",
+__all__ = ["GridPlan", "CadenceGraph", "autotune_tile", "compute_coords", "polconvert", "stream_copy", "RtsError", "library_path", "version", "GridFn", "DegridFn",
            "Chi2Fn", "grid", "degrid", "chi2"]
 
 
@@ -226,6 +226,40 @@ class GridPlan:
                                                _stream(stream)), "rts_grid_degrid")
         return model_out, grid_out, chi2_out
 
+    def grid_backward(self, vis, weights, grad_grid, want_weights=True, stream=None):
+        """Gradients through grid(vis, weights) (rts_grid_backward): returns
+        (w * D(grad_grid), Re(conj(vis) * D(grad_grid)) or None)."""
+        torch = _torch()
+        _check_dev(vis, "vis", torch.complex64, self._vis_shape())
+        _check_dev(weights, "weights", torch.float32, self._vis_shape())
+        _check_dev(grad_grid, "grad_grid", torch.complex64, self._grid_shape())
+        gv = torch.empty(self._vis_shape(), dtype=torch.complex64, device=vis.device)
+        gw = torch.empty(self._vis_shape(), dtype=torch.float32, device=vis.device) if want_weights else None
+        _lib.check(_lib.load().rts_grid_backward(self.handle, _ptr(vis), _ptr(weights), _ptr(grad_grid), _ptr(gv),
+                                                 _ptr(gw), _stream(stream)), "rts_grid_backward")
+        return gv, gw
+
+    def chi2_backward(self, vis, weights, model, grid_resid, grad_chi2, want=(True, True, True), stream=None):
+        """Gradients of the fused step's chi-squared (rts_chi2_backward): from the
+        model and the residual grid it wrote and dL/dchi2 (a float64 device scalar),
+        returns (dL/dvis, dL/dweights, dL/dgrid), each None where not wanted."""
+        torch = _torch()
+        _check_dev(vis, "vis", torch.complex64, self._vis_shape())
+        _check_dev(weights, "weights", torch.float32, self._vis_shape())
+        _check_dev(model, "model", torch.complex64, self._vis_shape())
+        _check_dev(grid_resid, "grid_resid", torch.complex64, self._grid_shape())
+        _check_dev(grad_chi2, "grad_chi2", torch.float64)
+        if grad_chi2.numel() != 1:
+            raise ValueError("grad_chi2 must hold one value")
+        dev = vis.device
+        gv = torch.empty(self._vis_shape(), dtype=torch.complex64, device=dev) if want[0] else None
+        gw = torch.empty(self._vis_shape(), dtype=torch.float32, device=dev) if want[1] else None
+        gg = torch.empty(self._grid_shape(), dtype=torch.complex64, device=dev) if want[2] else None
+        _lib.check(_lib.load().rts_chi2_backward(self.handle, _ptr(vis), _ptr(weights), _ptr(model),
+                                                 _ptr(grid_resid), _ptr(grad_chi2), _ptr(gv), _ptr(gw), _ptr(gg),
+                                                 _stream(stream)), "rts_chi2_backward")
+        return gv, gw, gg
+
     def cadence_graph(self, uvw, vis, weights, grid_in, model_out, grid_out, chi2_out, stream=None):
         """Capture [update(uvw, weights); grid_degrid(...)] once; see CadenceGraph."""
         return CadenceGraph(self, uvw, vis, weights, grid_in, model_out, grid_out, chi2_out, stream)
@@ -335,6 +369,16 @@ def polconvert(A, P, out=None, stream=None):
     _lib.check(_lib.load().rts_polconvert(_ptr(A), _ptr(P), _ptr(out), n, C, stride, _stream(stream)),
                "rts_polconvert")
     return out
+
+
+def stream_copy(src, dst, stream=None):
+    """Reference streaming copy src -> dst (device tensors of equal byte size,
+    16-byte aligned): the attainable-bandwidth figure beside throughput results."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous and of equal byte size")
+    _lib.check(_lib.load().rts_stream_copy(_ptr(src), _ptr(dst), n, _stream(stream)), "rts_stream_copy")
+    return dst
 
 
 def compute_coords(uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversample=8, stream=None):

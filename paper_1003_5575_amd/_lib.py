@@ -18,7 +18,8 @@ EXPORTED = (
     "rts_grid_plan", "rts_plan_update", "rts_grid", "rts_degrid", "rts_grid_degrid", "rts_compute_coords",
     "rts_cadence_graph_create", "rts_cadence_graph_launch", "rts_cadence_graph_destroy", "rts_autotune_tile",
     "rts_plan_valid_mask", "rts_image", "rts_polconvert", "rts_plan_set_baseline_kernels", "rts_plan_get_table",
-    "rts_plan_get_info", "rts_plan_destroy", "rts_last_error", "rts_version",
+    "rts_plan_get_info", "rts_plan_destroy", "rts_last_error", "rts_version", "rts_stream_copy",
+    "rts_grid_backward", "rts_chi2_backward",
 )
 
 
@@ -69,6 +70,9 @@ def load() -> ctypes.CDLL:
     lib.rts_plan_valid_mask.argtypes = [P, P, P]
     lib.rts_polconvert.argtypes = [P, P, P, I64, ctypes.c_int32, I64, P]
     lib.rts_plan_set_baseline_kernels.argtypes = [P, P, P]
+    lib.rts_stream_copy.argtypes = [P, P, I64, P]
+    lib.rts_grid_backward.argtypes = [P, P, P, P, P, P, P]
+    lib.rts_chi2_backward.argtypes = [P, P, P, P, P, P, P, P, P, P]
     lib.rts_cadence_graph_create.argtypes = [ctypes.POINTER(P), P, P, P, P, P, P, P, P, P]
     lib.rts_cadence_graph_launch.argtypes = [P, P]
     lib.rts_cadence_graph_destroy.argtypes = [P]
@@ -80,7 +84,7 @@ def load() -> ctypes.CDLL:
                  "rts_autotune_tile", "rts_grid_plan", "rts_plan_update", "rts_grid", "rts_degrid", "rts_grid_degrid", "rts_compute_coords",
                  "rts_cadence_graph_create", "rts_cadence_graph_launch", "rts_cadence_graph_destroy", "rts_autotune_tile",
     "rts_plan_valid_mask", "rts_image", "rts_polconvert", "rts_plan_set_baseline_kernels", "rts_plan_get_table",
-    "rts_plan_get_info", "rts_plan_destroy"):
+    "rts_plan_get_info", "rts_plan_destroy", "rts_stream_copy", "rts_grid_backward", "rts_chi2_backward"):
         getattr(lib, name).restype = I
     lib.rts_last_error.restype = ctypes.c_char_p
     lib.rts_last_error.argtypes = []

@@ -6,16 +6,27 @@ the backward pass of each is a call of the other:
 
   * DegridFn: M = D G;            dL/dG = D^T dL/dM        (rts_grid with w = 1)
   * GridFn:   G = D^T (w V);      dL/dV = w D(dL/dG),  dL/dw = Re(conj(V) D(dL/dG))
+                                  (rts_grid_backward)
   * Chi2Fn:   L = sum w |V - D G|^2 over valid samples, from one fused pass
               (rts_grid_degrid); dL/dG = -2 D^T(w r), dL/dw = |r|^2, dL/dV = 2 w r
+              (rts_chi2_backward, from the fused pass's model and grid)
 
 Gradients follow PyTorch's convention for complex tensors (dL/dRe + i dL/dIm).
-Every product runs in the library's HIP kernels; these classes only route
-tensors.
+The products, the residual and the element-wise gradient terms all run in the
+library's HIP kernels; these classes route tensors and allocate the outputs.
+Plans built with conjugate copies are rejected: their gridding also adds
+conj(w V) at -uv, which is not complex-linear in V, and their degridding
+predicts the +uv copy only.
 """
 from __future__ import annotations
 
 import torch
+
+
+def _linear_plan(plan):
+    if plan.params.conjugate:
+        raise ValueError("autograd needs a plan without conjugate copies (conjugate=False)")
+    return plan
 
 
 class DegridFn(torch.autograd.Function):
@@ -23,7 +34,7 @@ class DegridFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, G, plan):
-        ctx.plan = plan
+        ctx.plan = _linear_plan(plan)
         return plan.degrid(G.contiguous())
 
     @staticmethod
@@ -38,48 +49,38 @@ class GridFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, V, w, plan):
-        ctx.plan = plan
+        ctx.plan = _linear_plan(plan)
         ctx.save_for_backward(V, w)
         return plan.grid(V.contiguous(), w.contiguous())
 
     @staticmethod
     def backward(ctx, gG):
         V, w = ctx.saved_tensors
-        d = ctx.plan.degrid(gG.contiguous())          # 0 at invalid samples
-        gV = gw = None
-        if ctx.needs_input_grad[0]:
-            gV = d * w
-        if ctx.needs_input_grad[1]:
-            gw = (torch.conj(V) * d).real
-        return gV, gw, None
+        gV, gw = ctx.plan.grid_backward(V.contiguous(), w.contiguous(), gG.contiguous(),
+                                        want_weights=ctx.needs_input_grad[1])
+        return (gV if ctx.needs_input_grad[0] else None), gw, None
 
 
 class Chi2Fn(torch.autograd.Function):
     """chi2 = sum_i w_i |V_i - degrid(G)_i|^2 over valid samples (FP64 scalar).
 
     The forward is one fused pass that also grids the weighted residual, which is
-    exactly the gradient with respect to G; the backward only scales it."""
+    exactly the gradient with respect to G up to the factor -2; the backward forms
+    the three gradients from that grid and the model in one library call."""
 
     @staticmethod
     def forward(ctx, V, w, G, plan):
-        model, g_out, chi2 = plan.grid_degrid(V.contiguous(), w.contiguous(), G.contiguous())
-        # residual in place of the model (a buffer of this call): V - M, 0 where invalid
-        r = torch.sub(V, model, out=model)
-        r.masked_fill_(~plan.valid_mask(), 0)
-        ctx.save_for_backward(r, w, g_out)
+        ctx.plan = _linear_plan(plan)
+        V, w = V.contiguous(), w.contiguous()
+        model, g_out, chi2 = plan.grid_degrid(V, w, G.contiguous())
+        ctx.save_for_backward(V, w, model, g_out)
         return chi2
 
     @staticmethod
     def backward(ctx, g):
-        r, w, g_out = ctx.saved_tensors
-        g32 = g.to(torch.float32)
-        gV = gw = gG = None
-        if ctx.needs_input_grad[0]:
-            gV = (2.0 * g32) * w * r
-        if ctx.needs_input_grad[1]:
-            gw = torch.view_as_real(r).square().sum(-1).mul_(g32)
-        if ctx.needs_input_grad[2]:
-            gG = g_out * (-2.0 * g32)
+        V, w, model, g_out = ctx.saved_tensors
+        g = g.to(torch.float64).contiguous()
+        gV, gw, gG = ctx.plan.chi2_backward(V, w, model, g_out, g, want=tuple(ctx.needs_input_grad[:3]))
         return gV, gw, gG, None
 
 

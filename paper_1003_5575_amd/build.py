@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librtsgrid.so")
 SOURCES = ["abi.cpp", "runtime.cpp", "plan.hip", "tile_grid.hip", "tile_degrid.hip", "tile_fused.hip", "mfma_bf16x3.hip",
-           "imager.hip", "polconv.hip"]
+           "imager.hip", "polconv.hip", "memcopy.hip", "backward.hip"]
 ARCH = os.environ.get("RTSGRID_ARCH", "gfx950")
 
 

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <utility>
 
 #include "internal.h"
 
@@ -592,6 +593,73 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
   return RTS_OK;
 }
 
+rts_status rts_grid_backward(rts_plan_t plan, const float *vis, const float *weights, const float *grad_grid,
+                             float *grad_vis, float *grad_weights, void *stream) {
+  if (rts_status st = check_plan(plan)) return st;
+  if (plan->ncopy != 1) {
+    set_error("rts_grid_backward does not support plans built with conjugate=1");
+    return RTS_E_UNSUPPORTED;
+  }
+  RTS_REQUIRE(vis && weights && grad_grid && grad_vis, "vis, weights, grad_grid and grad_vis must be non-NULL");
+  RTS_REQUIRE(aligned(vis, 8) && aligned(weights, 4) && aligned(grad_grid, 8) && aligned(grad_vis, 8) &&
+                  aligned(grad_weights, 4),
+              "misaligned buffer");
+  const size_t n = (size_t)plan->C * plan->B * plan->T;
+  const size_t gbytes = (size_t)plan->C * plan->N * plan->N * 8;
+  auto apart = [](const void *p, size_t pb, const void *q, size_t qb) {
+    const char *a = (const char *)p, *b = (const char *)q;
+    return !a || !b || a + pb <= b || b + qb <= a;
+  };
+  RTS_REQUIRE(apart(grad_vis, 8 * n, vis, 8 * n) && apart(grad_vis, 8 * n, weights, 4 * n) &&
+                  apart(grad_vis, 8 * n, grad_grid, gbytes) && apart(grad_weights, 4 * n, vis, 8 * n) &&
+                  apart(grad_weights, 4 * n, weights, 4 * n) && apart(grad_weights, 4 * n, grad_grid, gbytes) &&
+                  apart(grad_weights, 4 * n, grad_vis, 8 * n),
+              "grad_vis / grad_weights overlap another buffer");
+  hipStream_t s = (hipStream_t)stream;
+  if (rts_status st = rts_degrid(plan, grad_grid, grad_vis, stream)) return st;
+  RTS_HIP(launch_grid_backward((const float2 *)vis, weights, (float2 *)grad_vis, grad_weights, (int64_t)n, s));
+  return RTS_OK;
+}
+
+rts_status rts_chi2_backward(rts_plan_t plan, const float *vis, const float *weights, const float *model,
+                             const float *grid_resid, const double *grad_chi2, float *grad_vis,
+                             float *grad_weights, float *grad_grid, void *stream) {
+  if (rts_status st = check_plan(plan)) return st;
+  if (plan->ncopy != 1) {
+    set_error("rts_chi2_backward does not support plans built with conjugate=1");
+    return RTS_E_UNSUPPORTED;
+  }
+  RTS_REQUIRE(grad_chi2 != nullptr, "grad_chi2 must be non-NULL");
+  RTS_REQUIRE(!(grad_vis || grad_weights) || (vis && weights && model),
+              "vis, weights and model are needed for grad_vis / grad_weights");
+  RTS_REQUIRE(!grad_grid || grid_resid, "grid_resid is needed for grad_grid");
+  RTS_REQUIRE(aligned(vis, 8) && aligned(weights, 4) && aligned(model, 8) && aligned(grid_resid, 16) &&
+                  aligned(grad_chi2, 8) && aligned(grad_vis, 8) && aligned(grad_weights, 4) && aligned(grad_grid, 16),
+              "misaligned buffer (grids need 16-byte alignment)");
+  const size_t n = (size_t)plan->C * plan->B * plan->T;
+  const size_t gbytes = (size_t)plan->C * plan->N * plan->N * 8;
+  auto apart = [](const void *p, size_t pb, const void *q, size_t qb) {
+    const char *a = (const char *)p, *b = (const char *)q;
+    return !a || !b || a + pb <= b || b + qb <= a;
+  };
+  const std::pair<const void *, size_t> ins[] = {{vis, 8 * n}, {weights, 4 * n}, {model, 8 * n}};
+  for (const auto &in : ins) {
+    RTS_REQUIRE(apart(grad_vis, 8 * n, in.first, in.second) && apart(grad_weights, 4 * n, in.first, in.second),
+                "grad_vis / grad_weights overlap an input");
+  }
+  RTS_REQUIRE(apart(grad_vis, 8 * n, grad_weights, 4 * n), "grad_vis and grad_weights overlap");
+  RTS_REQUIRE(apart(grad_grid, gbytes, vis, 8 * n) && apart(grad_grid, gbytes, model, 8 * n) &&
+                  apart(grad_grid, gbytes, weights, 4 * n) && apart(grad_grid, gbytes, grad_vis, 8 * n) &&
+                  apart(grad_grid, gbytes, grad_weights, 4 * n) && apart(grad_grid, gbytes, grad_chi2, 8),
+              "grad_grid overlaps another buffer");
+  RTS_REQUIRE(grad_grid == grid_resid || apart(grad_grid, gbytes, grid_resid, gbytes),
+              "grad_grid partly overlaps grid_resid");
+  RTS_HIP(launch_chi2_backward(*plan, (const float2 *)vis, weights, (const float2 *)model, grad_chi2,
+                               (float2 *)grad_vis, grad_weights, (const float2 *)grid_resid, (float2 *)grad_grid,
+                               (hipStream_t)stream));
+  return RTS_OK;
+}
+
 rts_status rts_compute_coords(const rts_params *params, const double *uvw_m, const double *freq_hz,
                               const float *weights, int32_t *out, void *stream) {
   if (rts_status st = validate(params)) return st;
@@ -617,6 +685,20 @@ rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream) {
   RTS_REQUIRE(mask != nullptr, "mask is NULL");
   const int64_t n = (int64_t)plan->C * plan->B * plan->T;
   RTS_HIP(launch_valid_mask(plan->d_coords, mask, plan->B, plan->T, plan->ncopy, n, (hipStream_t)stream));
+  return RTS_OK;
+}
+
+rts_status rts_stream_copy(const void *src, void *dst, int64_t bytes, void *stream) {
+  RTS_REQUIRE(bytes >= 0, "bytes must be >= 0");
+  if (bytes == 0) return RTS_OK;
+  RTS_REQUIRE(src && dst, "src and dst must be non-NULL");
+  RTS_REQUIRE(aligned(src, 16) && aligned(dst, 16), "src and dst must be 16-byte aligned");
+  const char *a = (const char *)src, *b = (const char *)dst;
+  RTS_REQUIRE(a + bytes <= b || b + bytes <= a, "src and dst overlap");
+  int dev = 0, n_cu = 256;
+  RTS_HIP(hipGetDevice(&dev));
+  RTS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  RTS_HIP(launch_stream_copy(src, dst, bytes, n_cu, (hipStream_t)stream));
   return RTS_OK;
 }
 

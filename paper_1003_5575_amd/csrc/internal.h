@@ -168,6 +168,12 @@ hipError_t launch_chi2_reduce(const double *part, int64_t n, double *out, hipStr
 hipError_t launch_valid_mask(const uint16_t *coords, uint8_t *mask, int B, int T, int ncopy, int64_t n,
                              hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, int n_cu, hipStream_t s);
+// gradient terms (backward.hip)
+hipError_t launch_grid_backward(const float2 *vis, const float *w, float2 *d, float *gw, int64_t n, hipStream_t s);
+hipError_t launch_chi2_backward(const Plan &P, const float2 *vis, const float *w, const float2 *model,
+                                const double *gchi2, float2 *gv, float *gw, const float2 *gres, float2 *gg,
+                                hipStream_t s);
 // Matrix-core path: largest LDS need of its kernels for this geometry (bytes),
 // per-baseline table size (words per table) and its construction.
 size_t mfma_lds_bytes(int WN, int OS2, int tile);

@@ -143,3 +143,46 @@ def test_chi2_gradients_through_matrix_core_plans(rts, prec, W, OS, tol):
         assert rel_l2(G.grad[c].cpu().numpy(), gG[c]) <= 4 * tol
         assert rel_l2(wt.grad[c].cpu().numpy(), gw[c]) <= 4 * tol
         assert rel_l2(V.grad[c].cpu().numpy(), gV[c]) <= 4 * tol
+
+
+def test_backward_entry_points_through_the_abi(rts):
+    """rts_grid_backward and rts_chi2_backward called directly, with an upstream
+    chi-squared gradient other than 1, against the oracle's analytic gradients."""
+    wl, freq, du, uvw, vis, w, plan, geom = setup(rts, seed=7)
+    rng = np.random.default_rng(7)
+    gGt = (rng.standard_normal((3, 256, 256)) + 1j * rng.standard_normal((3, 256, 256))).astype(np.complex64)
+    gV, gw = plan.grid_backward(vis, w, torch.from_numpy(gGt).cuda())
+    rV, rw = O.grid_vjp(geom, wl.vis, wl.weights, gGt.astype(np.complex128))
+    for c in range(3):
+        assert rel_l2(gV[c].cpu().numpy(), rV[c]) <= RTOL_L2
+        assert rel_l2(gw[c].cpu().numpy(), rw[c]) <= RTOL_L2
+    G0 = (0.1 * (rng.standard_normal((3, 256, 256)) + 1j * rng.standard_normal((3, 256, 256)))).astype(np.complex64)
+    model, gres, chi2 = plan.grid_degrid(vis, w, torch.from_numpy(G0).cuda())
+    g = torch.tensor(0.37, dtype=torch.float64, device="cuda")
+    bV, bw, bG = plan.chi2_backward(vis, w, model, gres, g)
+    chi2o, oG, ow, oV = O.chi2_gradients(geom, wl.vis, wl.weights, G0.astype(np.complex128))
+    for c in range(3):
+        assert rel_l2(bG[c].cpu().numpy(), 0.37 * oG[c]) <= RTOL_L2
+        assert rel_l2(bw[c].cpu().numpy(), 0.37 * ow[c]) <= RTOL_L2
+        assert rel_l2(bV[c].cpu().numpy(), 0.37 * oV[c]) <= RTOL_L2
+    assert torch.all(bV.cpu()[~torch.from_numpy(geom.valid)] == 0)
+
+
+def test_conjugate_plans_are_rejected(rts):
+    """Gridding with conjugate copies adds conj(w V) at -uv, which is not
+    complex-linear in V: the autograd functions and the backward entry points
+    refuse such plans instead of returning a wrong adjoint."""
+    wl, freq, du = small_case(seed=8, n_ant=30, channels=(0, 9), N=128)
+    uvw, vis, w = to_dev(torch, wl)
+    plan = rts.GridPlan(uvw, freq, w, 128, du, conjugate=True)
+    G = torch.zeros((2, 128, 128), dtype=torch.complex64, device="cuda")
+    for f in (lambda: rts.grid(vis, w, plan), lambda: rts.degrid(G, plan), lambda: rts.chi2(vis, w, G, plan)):
+        with pytest.raises(ValueError):
+            f()
+    with pytest.raises(rts.RtsError) as ei:
+        plan.grid_backward(vis, w, G)
+    assert ei.value.status == 4                      # RTS_E_UNSUPPORTED
+    g = torch.ones((), dtype=torch.float64, device="cuda")
+    with pytest.raises(rts.RtsError) as ei:
+        plan.chi2_backward(vis, w, vis.clone(), G, g)
+    assert ei.value.status == 4

@@ -2,10 +2,19 @@
 
 The oracle's image is pinned in tests/test_oracle_pins.py against a brute-force
 direct DFT; here the GPU image (hipFFT batched inverse transform between the
-library's sign and grid-correction passes) must match it per channel within the
-FP32 bound (1e-5, or four times the error of a plain complex64 CPU FFT of the
-same grid where the single-precision transform itself rounds more), for odd and
-even supports, in place and out of place."""
+library's sign and grid-correction passes) must match it per channel, for odd and
+even supports, in place and out of place.
+
+Bounds (relative L2 per channel):
+  * central region |nu_x|, |nu_y| <= 1/4: <= 1e-5.  There the correction divides
+    by khat(nu) >= 0.12 khat(0) (W = 16; 0.55 at W = 7), so FP32 rounding of the
+    transform is amplified at most eightfold.
+  * whole field with the correction undone on both sides (multiplied back by the
+    exact FP64 khat(nu_y) khat(nu_x)): <= 1e-5.  This checks the transform, the
+    two centring sign passes and every correction value over all pixels, without
+    the division by khat values down to 1e-4 of khat(0) at the field edge (W = 16),
+    which lifts the single-precision rounding of any FP32 implementation there.
+"""
 import numpy as np
 import pytest
 
@@ -34,19 +43,25 @@ def test_image_matches_oracle(rts, W, OS, N, conj):
     img = plan.image(G).cpu().numpy()
     G64 = G.cpu().numpy().astype(np.complex128)
     ref = O.image(G64, W, O.default_beta(W))
-    # The FP32 2-D FFT itself rounds at each of its log2(N^2) stages; its error
-    # is measured with a plain complex64 CPU pipeline of the same operation
-    # (numpy's FFT in single precision), and the GPU must be within 4x of it.
+    # A plain complex64 CPU pipeline of the same operation (numpy's FFT in single
+    # precision) is printed beside the GPU errors for comparison.
     nu = (np.arange(N) - N // 2) / N
     corr = O.kb_hat(nu, W, O.default_beta(W)).astype(np.float32)
     G32 = G.cpu().numpy()
     ref32 = (np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(G32, axes=(-2, -1)).astype(np.complex64)).astype(np.complex64),
                              axes=(-2, -1)) * np.float32(N * N)) / (corr[:, None] * corr[None, :])
+    q = slice(N // 4, 3 * N // 4 + 1)                    # |nu| <= 1/4
+    k64 = O.kb_hat(nu, W, O.default_beta(W))
+    kk = k64[:, None] * k64[None, :]
     for c in range(len(freq)):
         e32 = rel_l2(ref32[c], ref[c])
         err = rel_l2(img[c], ref[c])
-        print(f"imager W={W} N={N} channel {c}: rel L2 {err:.2e} (complex64 CPU FFT: {e32:.2e})")
-        assert err <= max(RTOL_L2, 4 * e32), f"channel {c}"
+        err_c = rel_l2(img[c][q, q], ref[c][q, q])
+        err_u = rel_l2(img[c] * kk, ref[c] * kk)
+        print(f"imager W={W} N={N} channel {c}: central {err_c:.2e}, uncorrected {err_u:.2e}, "
+              f"whole field {err:.2e} (complex64 CPU FFT: {e32:.2e})")
+        assert err_c <= RTOL_L2, f"channel {c}: central region"
+        assert err_u <= RTOL_L2, f"channel {c}: whole field without the correction"
     if conj:
         # Hermitian grid -> real image.  Checked on the central half of the field:
         # towards the edges the grid correction divides by khat values down to
