@@ -149,7 +149,8 @@ rts_status rts_grid(rts_plan_t plan, const float *vis, const float *weights, flo
  * written. */
 rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *stream);
 
-/* Fused residual step: M = degrid(grid_in); r = V - M (0 where invalid);
+/* Fused residual step (Eq. (1) and its adjoint, composed as one model-fitting
+ * iteration): M = degrid(grid_in); r = V - M (0 where invalid);
  * grid_out = grid(r, w); chi2 = sum_i w_i |r_i|^2 (FP64).  model_out (C*B*T
  * complex64) and chi2_out (one double in device memory) may be NULL, except that
  * matrix-core plans need model_out (RTS_E_INVALID otherwise).  grid_in and
@@ -161,6 +162,28 @@ rts_status rts_degrid(rts_plan_t plan, const float *grid, float *vis_out, void *
 rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weights,
                            const float *grid_in, float *model_out, float *grid_out,
                            double *chi2_out, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): rts_grid_plan followed
+ * by rts_grid_degrid in one call, with the plan's workspace carved from a static
+ * device array of the library (64 MiB per device, held until the process ends)
+ * instead of allocated.  Same arguments and results as those two calls for an
+ * FP32 plan (params->precision RTS_PREC_FP32, conjugate 0, support <= 16,
+ * schedule ignored: one workgroup per (channel, tile)); freq_hz is host memory,
+ * every other buffer device memory owned by the caller.  The work list is sized
+ * for the worst case (four listings per sample), so nothing is dropped.  Returns
+ * RTS_E_INVALID with a message naming the bytes needed when the problem does not
+ * fit the static array (about 34 bytes per sample plus 20 per (channel, tile)
+ * pair; the benchmark-sized problems do not fit: use rts_grid_plan +
+ * rts_grid_degrid there).  Calls no hipMalloc, hipFree or allocating library
+ * routine and does not synchronise; its kernel table and per-channel scales
+ * reach the device as kernel arguments.  Every call on one device shares that
+ * device's array, so calls that overlap on one device (on different streams, or
+ * from several threads) race: serialise them.  Each call re-initialises what it
+ * reads from the array. */
+rts_status rts_grid_degrid_noalloc(const rts_params *params, const double *uvw_m, const double *freq_hz,
+                                   const float *weights, const float *vis, const float *grid_in, float *model_out,
+                                   float *grid_out, double *chi2_out, void *stream);
 
 /* Backward of gridding, for automatic differentiation of Eq. (1): with D the
  * plan's degridding (the adjoint of its gridding without weights),

@@ -397,4 +397,34 @@ def compute_coords(uvw, freq_hz, weights, n_grid, cell_lambda, support=7, oversa
     return out
 
 
+def grid_degrid_noalloc(uvw, freq_hz, weights, vis, grid_in, n_grid, cell_lambda, support=7, oversample=8,
+                        beta=None, tile=0, model_out=None, grid_out=None, chi2_out=None, stream=None):
+    """Plan and fused residual step in one call of rts_grid_degrid_noalloc, whose
+    workspace is the library's static device array (no device allocation inside
+    the call).  Outputs are caller tensors (allocated here when not given).
+    Returns (model_out or None, grid_out, chi2_out or None)."""
+    torch = _torch()
+    _check_dev(uvw, "uvw", torch.float64)
+    B, T = int(uvw.shape[0]), int(uvw.shape[1])
+    freq = [float(f) for f in freq_hz]
+    C = len(freq)
+    _check_dev(weights, "weights", torch.float32, (C, B, T))
+    _check_dev(vis, "vis", torch.complex64, (C, B, T))
+    _check_dev(grid_in, "grid_in", torch.complex64, (C, n_grid, n_grid))
+    if grid_out is None:
+        grid_out = torch.empty((C, n_grid, n_grid), dtype=torch.complex64, device=vis.device)
+    _check_dev(grid_out, "grid_out", torch.complex64, (C, n_grid, n_grid))
+    if model_out is not None:
+        _check_dev(model_out, "model_out", torch.complex64, (C, B, T))
+    if chi2_out is not None:
+        _check_dev(chi2_out, "chi2_out", torch.float64)
+    p = make_params(n_grid, cell_lambda, support, oversample, C, B, T, beta=beta, tile=tile)
+    fr = (ctypes.c_double * C)(*freq)
+    _lib.check(_lib.load().rts_grid_degrid_noalloc(ctypes.byref(p), _ptr(uvw), ctypes.cast(fr, ctypes.c_void_p),
+                                                   _ptr(weights), _ptr(vis), _ptr(grid_in), _ptr(model_out),
+                                                   _ptr(grid_out), _ptr(chi2_out), _stream(stream)),
+               "rts_grid_degrid_noalloc")
+    return model_out, grid_out, chi2_out
+
+
 from .autograd import Chi2Fn, DegridFn, GridFn, chi2, degrid, grid  # noqa: E402,F401

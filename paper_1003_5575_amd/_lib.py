@@ -19,7 +19,7 @@ EXPORTED = (
     "rts_cadence_graph_create", "rts_cadence_graph_launch", "rts_cadence_graph_destroy", "rts_autotune_tile",
     "rts_plan_valid_mask", "rts_image", "rts_polconvert", "rts_plan_set_baseline_kernels", "rts_plan_get_table",
     "rts_plan_get_info", "rts_plan_destroy", "rts_last_error", "rts_version", "rts_stream_copy",
-    "rts_grid_backward", "rts_chi2_backward",
+    "rts_grid_backward", "rts_chi2_backward", "rts_grid_degrid_noalloc",
 )
 
 
@@ -67,6 +67,7 @@ def load() -> ctypes.CDLL:
     lib.rts_degrid.argtypes = [P, P, P, P]
     lib.rts_grid_degrid.argtypes = [P, P, P, P, P, P, P, P]
     lib.rts_compute_coords.argtypes = [ctypes.POINTER(RtsParams), P, P, P, P, P]
+    lib.rts_grid_degrid_noalloc.argtypes = [ctypes.POINTER(RtsParams), P, P, P, P, P, P, P, P, P]
     lib.rts_plan_valid_mask.argtypes = [P, P, P]
     lib.rts_polconvert.argtypes = [P, P, P, I64, ctypes.c_int32, I64, P]
     lib.rts_plan_set_baseline_kernels.argtypes = [P, P, P]
@@ -84,7 +85,8 @@ def load() -> ctypes.CDLL:
                  "rts_autotune_tile", "rts_grid_plan", "rts_plan_update", "rts_grid", "rts_degrid", "rts_grid_degrid", "rts_compute_coords",
                  "rts_cadence_graph_create", "rts_cadence_graph_launch", "rts_cadence_graph_destroy", "rts_autotune_tile",
     "rts_plan_valid_mask", "rts_image", "rts_polconvert", "rts_plan_set_baseline_kernels", "rts_plan_get_table",
-    "rts_plan_get_info", "rts_plan_destroy", "rts_stream_copy", "rts_grid_backward", "rts_chi2_backward"):
+    "rts_plan_get_info", "rts_plan_destroy", "rts_stream_copy", "rts_grid_backward", "rts_chi2_backward",
+                 "rts_grid_degrid_noalloc"):
         getattr(lib, name).restype = I
     lib.rts_last_error.restype = ctypes.c_char_p
     lib.rts_last_error.argtypes = []

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <utility>
 
@@ -140,33 +141,82 @@ int choose_seg_max(int W, int T) {
   return 2;
 }
 
-void fill_tables(Plan &P) {
+// Kernel tables of a plan's geometry into caller storage: tab [OS][W], the
+// extended table tabE [2*OS][WNP] (zeroed first) and, when hi and lo are given,
+// the BF16 hi / lo split of tabE for the matrix-core path.
+void fill_tables_raw(const Plan &P, float *tab, float *tabE, uint16_t *hi, uint16_t *lo) {
   const int W = P.W, OS = P.OS;
-  P.tab.assign((size_t)OS * W, 0.0f);
   for (int p = 0; p < OS; ++p)
     for (int j = 0; j < W; ++j) {
       const int r = P.r0 + p, t = j - P.h_lo;
-      P.tab[(size_t)p * W + j] = (float)kaiser_bessel((double)t - (double)r / OS, W, P.beta);
+      tab[(size_t)p * W + j] = (float)kaiser_bessel((double)t - (double)r / OS, W, P.beta);
     }
   // Extended table over the (W+1)-wide window: row s = d*OS + p holds the weights
   // of window columns 0..W for a sample whose cell is d in {0,1} past the window's
   // first tap position, with phase row p.
-  P.tabE.assign((size_t)2 * OS * P.WNP, 0.0f);
-  P.tab_hi.assign((size_t)2 * OS * P.WNP, 0);
-  P.tab_lo.assign((size_t)2 * OS * P.WNP, 0);
+  for (size_t i = 0; i < (size_t)2 * OS * P.WNP; ++i) {
+    tabE[i] = 0.0f;
+    if (hi && lo) hi[i] = lo[i] = 0;
+  }
   for (int d = 0; d < 2; ++d)
     for (int p = 0; p < OS; ++p)
       for (int i = 0; i < P.WN; ++i) {
         const int j = i - d;
         if (j >= 0 && j < W) {
           const size_t e = (size_t)(d * OS + p) * P.WNP + i;
-          P.tabE[e] = P.tab[(size_t)p * W + j];
-          // BF16 hi + lo split of the FP64 kernel value, for the matrix-core path
-          const double k = kaiser_bessel((double)(j - P.h_lo) - (double)(P.r0 + p) / OS, W, P.beta);
-          P.tab_hi[e] = bf16_bits((float)k);
-          P.tab_lo[e] = bf16_bits((float)(k - (double)bf16_value(P.tab_hi[e])));
+          tabE[e] = tab[(size_t)p * W + j];
+          if (hi && lo) {
+            // BF16 hi + lo split of the FP64 kernel value, for the matrix-core path
+            const double k = kaiser_bessel((double)(j - P.h_lo) - (double)(P.r0 + p) / OS, W, P.beta);
+            hi[e] = bf16_bits((float)k);
+            lo[e] = bf16_bits((float)(k - (double)bf16_value(hi[e])));
+          }
         }
       }
+}
+
+void fill_tables(Plan &P) {
+  P.tab.assign((size_t)P.OS * P.W, 0.0f);
+  P.tabE.assign((size_t)2 * P.OS * P.WNP, 0.0f);
+  P.tab_hi.assign(P.tabE.size(), 0);
+  P.tab_lo.assign(P.tabE.size(), 0);
+  fill_tables_raw(P, P.tab.data(), P.tabE.data(), P.tab_hi.data(), P.tab_lo.data());
+}
+
+// Plan fields that follow from the parameters alone (no allocation): geometry,
+// tile edge and samples per segment.
+rts_status init_geometry(Plan &P, const rts_params *params) {
+  P.p = *params;
+  P.N = params->n_grid; P.W = params->support; P.OS = params->oversample;
+  P.WN = P.W + 1;
+  P.WNP = (P.WN + 3) & ~3;
+  P.C = params->n_chan; P.B = params->n_base; P.T = params->n_time;
+  P.ncopy = 1 + params->conjugate;
+  P.r0 = (P.W & 1) ? -(P.OS / 2) : 0;
+  P.h_lo = (P.W & 1) ? (P.W - 1) / 2 : P.W / 2 - 1;
+  P.beta = params->beta > 0.0 ? params->beta : 2.34 * P.W;
+  P.precision = params->precision;
+  P.tile = params->tile ? params->tile : choose_tile(P.N, P.WN);   // 64, 32 or 16
+  if (P.tile == 0 || (mfma_precision(P.precision) && P.tile % 16 != 0)) {
+    set_error("no legal tile size for n_grid=%d support=%d", P.N, P.W);
+    return RTS_E_UNSUPPORTED;
+  }
+  P.nT = P.N / P.tile;
+  P.nT2 = P.nT * P.nT;
+  P.nkeys = (int64_t)P.C * P.nT2;
+  RTS_REQUIRE(P.nkeys < ((int64_t)1 << 31), "too many (channel, tile) pairs");
+  P.seg_max = choose_seg_max(P.W, P.T);
+  // supports beyond the FP32 tile kernels' range run on the matrix-core path only
+  if (P.W <= kMaxW && !tile_supported(P.W, P.seg_max)) {
+    set_error("support %d is not instantiated", P.W);
+    return RTS_E_UNSUPPORTED;
+  }
+  if (mfma_precision(P.precision) && mfma_lds_bytes(P.WN, 2 * P.OS, P.tile) > 65536) {
+    set_error("support %d, oversample %d and tile %d need more than 64 KiB of LDS on the matrix-core path",
+              P.W, P.OS, P.tile);
+    return RTS_E_UNSUPPORTED;
+  }
+  return RTS_OK;
 }
 
 void free_plan(Plan *P) {
@@ -198,8 +248,8 @@ int chunk_channels(int nT2) { return std::max(1, std::min(kMaxCg, 8192 / nT2)); 
 
 // Choose the chunked counting sort when the tracks are short enough for the lane
 // path and one channel's tiles fit the LDS histogram; the (key, chunk) count
-// matrix is kept near 4M entries.
-void choose_sort(Plan &P) {
+// matrix is kept near 4M entries (max_hist entries at most).
+void choose_sort(Plan &P, int64_t max_hist = (int64_t)8 << 20) {
   P.nbx = 0;
   P.chunk = 0;
   P.cg = 1;
@@ -209,7 +259,7 @@ void choose_sort(Plan &P) {
   const int64_t per_iter = kBlock / g;
   const int64_t ntr = (int64_t)P.ncopy * P.B;
   const int64_t max_nbx = std::max<int64_t>(1, (ntr + per_iter - 1) / per_iter);
-  const int64_t cap_nbx = std::max<int64_t>(1, (8 << 20) / P.nkeys);
+  const int64_t cap_nbx = std::max<int64_t>(1, max_hist / P.nkeys);
   // The most channels per workgroup (uvw reuse) that still gives >= 1024 workgroups.
   int64_t nbx = 1;
   for (int cg = chunk_channels(P.nT2); cg >= 1; cg /= 2) {
@@ -338,6 +388,105 @@ hipError_t launch_tile(int mode, const Plan &P, const TileArgs &a, hipStream_t s
   }
 }
 
+// ------------------------------------------------ allocation-free fused step
+// Workspace of rts_grid_degrid_noalloc: one static array per device, held from
+// the library's load until the process ends.  Host code never uses the array's
+// name as an address: its device address is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_addr.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+
+// Device address of the current device's scratch array (looked up on the first
+// call on each device, with that device current).
+hipError_t scratch_addr(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
+// Small host values reach the device as kernel arguments (no host buffer has to
+// outlive the call and no copy engine is involved): 240 words per launch.
+constexpr int kWordsPerStore = 240;
+struct StoreWords {
+  uint32_t w[kWordsPerStore];
+};
+
+__global__ __launch_bounds__(256) void k_store_words(uint32_t *dst, StoreWords v, int n) {
+  if ((int)threadIdx.x < n) dst[threadIdx.x] = v.w[threadIdx.x];
+}
+
+hipError_t store_words(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 4;
+  const unsigned char *b = (const unsigned char *)src;
+  for (size_t i = 0; i < n; i += kWordsPerStore) {
+    StoreWords v{};
+    const int m = (int)std::min<size_t>(kWordsPerStore, n - i);
+    std::memcpy(v.w, b + 4 * i, 4 * (size_t)m);
+    hipLaunchKernelGGL(k_store_words, dim3(1), dim3(256), 0, s, (uint32_t *)dst + i, v, m);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Bump allocator over the scratch array (256-byte aligned regions).
+struct Carve {
+  unsigned char *base;
+  size_t used = 0;
+  template <class T>
+  T *take(size_t n) {
+    used = (used + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+    used += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// Lays the plan workspace out in `base` (nullptr: only measure) and returns the
+// bytes it needs.  The work list holds the worst case, four listings per sample
+// (every segment has at least one sample and touches at most 2 x 2 tiles), so no
+// listing can be dropped.
+size_t carve_plan(Plan &P, unsigned char *base, int64_t max_hist) {
+  Carve cv{base};
+  const int64_t nsamp = (int64_t)P.C * P.B * P.T;
+  choose_sort(P, max_hist);
+  P.scan_blocks = (P.nkeys + 4095) / 4096;
+  P.d_tabE = cv.take<float>((size_t)2 * P.OS * P.WNP);
+  P.d_scale = cv.take<double>((size_t)P.C);
+  P.d_stats = cv.take<unsigned long long>(8);
+  P.d_tile_off = cv.take<uint32_t>((size_t)P.nkeys + 1);
+  P.d_cursor = cv.take<uint32_t>((size_t)P.nkeys);
+  P.d_scan_tmp = cv.take<uint32_t>((size_t)P.scan_blocks + 1);
+  P.d_chi2_part = cv.take<double>((size_t)P.nkeys);
+  P.d_coords = cv.take<uint16_t>((size_t)nsamp);
+  if (P.nbx > 0) {
+    P.d_desc = cv.take<uint32_t>((size_t)P.C * P.B);
+    P.d_hist = cv.take<uint32_t>((size_t)P.nbx * P.nkeys);
+  }
+  P.list_cap = 4 * nsamp;
+  P.d_list = cv.take<uint2>((size_t)P.list_cap);
+  return cv.used;
+}
+
+}  // namespace
+
 hipError_t prepare_tile_kernels(const Plan &P) {
   TileArgs a{};
   a.OS2 = 2 * P.OS;
@@ -374,36 +523,7 @@ rts_status rts_grid_plan(rts_plan_t *out, const rts_params *params, const double
     set_error("host allocation failed");
     return RTS_E_NOMEM;
   }
-  P->p = *params;
-  P->N = params->n_grid; P->W = params->support; P->OS = params->oversample;
-  P->WN = P->W + 1;
-  P->WNP = (P->WN + 3) & ~3;
-  P->C = params->n_chan; P->B = params->n_base; P->T = params->n_time;
-  P->ncopy = 1 + params->conjugate;
-  P->r0 = (P->W & 1) ? -(P->OS / 2) : 0;
-  P->h_lo = (P->W & 1) ? (P->W - 1) / 2 : P->W / 2 - 1;
-  P->beta = params->beta > 0.0 ? params->beta : 2.34 * P->W;
-  P->precision = params->precision;
-  P->tile = params->tile ? params->tile : choose_tile(P->N, P->WN);   // 64, 32 or 16
-  if (P->tile == 0 || (mfma_precision(P->precision) && P->tile % 16 != 0)) {
-    set_error("no legal tile size for n_grid=%d support=%d", P->N, P->W);
-    return RTS_E_UNSUPPORTED;
-  }
-  P->nT = P->N / P->tile;
-  P->nT2 = P->nT * P->nT;
-  P->nkeys = (int64_t)P->C * P->nT2;
-  RTS_REQUIRE(P->nkeys < ((int64_t)1 << 31), "too many (channel, tile) pairs");
-  P->seg_max = choose_seg_max(P->W, P->T);
-  // supports beyond the FP32 tile kernels' range run on the matrix-core path only
-  if (P->W <= kMaxW && !tile_supported(P->W, P->seg_max)) {
-    set_error("support %d is not instantiated", P->W);
-    return RTS_E_UNSUPPORTED;
-  }
-  if (mfma_precision(P->precision) && mfma_lds_bytes(P->WN, 2 * P->OS, P->tile) > 65536) {
-    set_error("support %d, oversample %d and tile %d need more than 64 KiB of LDS on the matrix-core path",
-              P->W, P->OS, P->tile);
-    return RTS_E_UNSUPPORTED;
-  }
+  if (rts_status st = init_geometry(*P, params)) return st;
   fill_tables(*P);
   RTS_HIP(hipGetDevice(&P->device));
   RTS_HIP(hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, P->device));
@@ -590,6 +710,98 @@ rts_status rts_grid_degrid(rts_plan_t plan, const float *vis, const float *weigh
   }
   RTS_HIP(launch_tile(kFused, *plan, a, s));
   if (chi2_out) RTS_HIP(launch_chi2_reduce(plan->d_chi2_part, plan->nkeys, chi2_out, s));
+  return RTS_OK;
+}
+
+rts_status rts_grid_degrid_noalloc(const rts_params *params, const double *uvw_m, const double *freq_hz,
+                                   const float *weights, const float *vis, const float *grid_in, float *model_out,
+                                   float *grid_out, double *chi2_out, void *stream) {
+  if (rts_status st = validate(params)) return st;
+  RTS_REQUIRE(params->precision == RTS_PREC_FP32, "rts_grid_degrid_noalloc supports FP32 plans only");
+  if (params->conjugate) {
+    set_error("rts_grid_degrid_noalloc does not support conjugate=1 (as rts_grid_degrid)");
+    return RTS_E_UNSUPPORTED;
+  }
+  RTS_REQUIRE(uvw_m && freq_hz && weights && vis && grid_in && grid_out,
+              "uvw_m, freq_hz, weights, vis, grid_in and grid_out must be non-NULL");
+  RTS_REQUIRE(aligned(uvw_m, 8) && aligned(weights, 4) && aligned(vis, 8) && aligned(grid_in, 8) &&
+                  aligned(grid_out, 16) && aligned(model_out, 8) && aligned(chi2_out, 8),
+              "misaligned buffer");
+  for (int c = 0; c < params->n_chan; ++c)
+    RTS_REQUIRE(std::isfinite(freq_hz[c]) && freq_hz[c] > 0.0, "freq_hz[%d] must be > 0", c);
+  Plan P;   // host-side description only: its device arrays are carved from the scratch array
+  if (rts_status st = init_geometry(P, params)) return st;
+  RTS_REQUIRE(P.W <= kMaxW, "rts_grid_degrid_noalloc supports support <= %d", kMaxW);
+  P.schedule = RTS_SCHEDULE_TILES;
+  const size_t n = (size_t)P.C * P.B * P.T;
+  const size_t gbytes = (size_t)P.C * P.N * P.N * 8;
+  const char *gi = (const char *)grid_in, *go = (const char *)grid_out;
+  RTS_REQUIRE(gi + gbytes <= go || go + gbytes <= gi, "grid_in and grid_out overlap");
+  if (model_out) {
+    const char *m = (const char *)model_out;
+    auto apart = [&](const void *p, size_t bytes) {
+      const char *q = (const char *)p;
+      return m + 8 * n <= q || q + bytes <= m;
+    };
+    RTS_REQUIRE(apart(vis, 8 * n) && apart(weights, 4 * n) && apart(grid_in, gbytes) && apart(grid_out, gbytes),
+                "model_out overlaps vis, weights, grid_in or grid_out");
+  }
+  // Size check before any device work: everything but the chunked sort's count
+  // matrix must fit; the matrix then takes at most a quarter of what is left.
+  int64_t max_hist = 1;
+  {
+    Plan Q = P;
+    const size_t with_one = carve_plan(Q, nullptr, 1);
+    const size_t hist_one = Q.nbx > 0 ? (size_t)Q.nbx * Q.nkeys * 4 + 256 : 0;
+    const size_t fixed = with_one - hist_one;
+    RTS_REQUIRE(fixed <= kScratchBytes,
+                "this problem needs %zu bytes of plan workspace; rts_grid_degrid_noalloc has %zu "
+                "(use rts_grid_plan + rts_grid_degrid)", fixed, kScratchBytes);
+    max_hist = std::max<int64_t>(((int64_t)kScratchBytes - (int64_t)fixed) / 16 - 64, 1);
+  }
+  int dev = 0;
+  RTS_HIP(hipGetDevice(&dev));
+  RTS_HIP(hipDeviceGetAttribute(&P.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  P.device = dev;
+  RTS_HIP(prepare_tile_kernels(P));
+  void *base = nullptr;
+  RTS_HIP(scratch_addr(&base));
+  const size_t need = carve_plan(P, (unsigned char *)base, max_hist);
+  RTS_REQUIRE(need <= kScratchBytes,
+              "this problem needs %zu bytes of plan workspace; rts_grid_degrid_noalloc has %zu "
+              "(use rts_grid_plan + rts_grid_degrid)", need, kScratchBytes);
+  hipStream_t s = (hipStream_t)stream;
+  // kernel table and per-channel scales, as kernel arguments
+  {
+    float tab[kMaxOS * kMaxW];
+    float tabE[2 * kMaxOS * ((kMaxW + 1 + 3) & ~3)];
+    fill_tables_raw(P, tab, tabE, nullptr, nullptr);
+    RTS_HIP(store_words(P.d_tabE, tabE, (size_t)2 * P.OS * P.WNP * sizeof(float), s));
+    double sc[kWordsPerStore / 2];
+    for (int c0 = 0; c0 < P.C; c0 += kWordsPerStore / 2) {
+      const int m = std::min(P.C - c0, kWordsPerStore / 2);
+      for (int i = 0; i < m; ++i) sc[i] = freq_hz[c0 + i] / (kCLight * params->cell_lambda);
+      RTS_HIP(store_words(P.d_scale + c0, sc, (size_t)m * sizeof(double), s));
+    }
+  }
+  // plan: coordinates, segments, counting sort (as rts_plan_update)
+  PlanArgs pa = plan_args(P, uvw_m, weights);
+  RTS_HIP(launch_fill_u32(P.d_cursor, P.nkeys, 0u, s));
+  RTS_HIP(launch_fill_u32((uint32_t *)P.d_stats, 16, 0u, s));
+  RTS_HIP(launch_plan_count(pa, s));
+  RTS_HIP(scan_counts(P, s));
+  RTS_HIP(launch_plan_scatter(pa, s));
+  // fused residual step (as rts_grid_degrid)
+  TileArgs a = tile_args(P);
+  a.vis = (const float2 *)vis;
+  a.w = weights;
+  a.gin = (const float2 *)grid_in;
+  a.gout = (float2 *)grid_out;
+  a.model = (float2 *)model_out;
+  a.write_model = model_out != nullptr;
+  a.vec = vector_ok(P, vis, weights, model_out);
+  RTS_HIP(launch_tile(kFused, P, a, s));
+  if (chi2_out) RTS_HIP(launch_chi2_reduce(P.d_chi2_part, P.nkeys, chi2_out, s));
   return RTS_OK;
 }
 
