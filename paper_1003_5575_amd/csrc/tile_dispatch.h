@@ -28,16 +28,17 @@ namespace rts {
       hipLaunchKernelGGL((k_tile<WNV, SM, MODE, BLK, GRP>), dim3(nblk), dim3(BLK), lds, s, a);  \
     }                                                                                          \
   }
-#ifndef RTS_TILE64_BLOCK
-#define RTS_TILE64_BLOCK 256
-#endif
-// Small tiles with windows up to 8 cells use 128-thread workgroups (128
-// registers, four waves per SIMD); everything else 256-thread workgroups with
-// the 256-register budget (wider windows would spill with 128).
+// Windows up to 8 cells run with 128 registers and four waves per SIMD: small
+// tiles in 128-thread workgroups, larger tiles in 512-thread workgroups (two per
+// compute unit, which is what the LDS of the FP64 accumulator allows, so eight
+// waves per CU instead of four: the batched workload's four-sample segments are
+// latency-bound).  Wider windows use 256-thread workgroups with the 256-register
+// budget (they would spill with 128).
 #define RTS_TILE_CASE(WNV, SM)                                                        \
   case (WNV)*16 + (SM):                                                               \
-    if (P.tile <= 32 && (WNV) <= 8) RTS_TILE_LAUNCH(WNV, SM, ((WNV) <= 8 ? 128 : 256), 4) \
-    else RTS_TILE_LAUNCH(WNV, SM, RTS_TILE64_BLOCK, 4)                                    \
+    if ((WNV) <= 8 && P.tile <= 32) RTS_TILE_LAUNCH(WNV, SM, 128, 4)                  \
+    else if ((WNV) <= 8) RTS_TILE_LAUNCH(WNV, SM, 512, 4)                             \
+    else RTS_TILE_LAUNCH(WNV, SM, 256, 4)                                             \
     break;
 
 template <int MODE>

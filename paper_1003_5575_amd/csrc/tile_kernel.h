@@ -33,9 +33,10 @@ typedef float rts_nt_v4f __attribute__((ext_vector_type(4)));
 // update in registers, and the degridded value of each sample is the sum of the
 // group's partial sums (butterfly steps inside the group of lanes).
 // Minimum waves per SIMD the register allocation of the tile kernel targets for
-// small tiles (128-thread workgroups).  64-cell tiles hold a 64 KiB FP64
-// accumulator, so at most two of their 256-thread workgroups share a CU (two
-// waves per SIMD) and the kernel may use up to 256 registers.
+// 128- and 512-thread workgroups (128 registers).  64-cell tiles hold a 64 KiB
+// FP64 accumulator, so at most two of their workgroups share a CU; with windows
+// wider than 8 cells they run 256-thread workgroups (two waves per SIMD) that
+// may use up to 256 registers.
 #ifndef RTS_TILE_WAVES
 #define RTS_TILE_WAVES 4
 #endif
