@@ -447,7 +447,8 @@ def cpu_baseline_and_parity(args, wl, gin, gout, model, N, W, OS):
     from oracle import oracle as O
     ocpu.load()
     C = wl.vis.shape[0]
-    defaults = {"batched": (64, 8), "single_cadence": (32, 2), "differentiated": (32, 2), "tiny": (1, 1)}
+    # about 10-30 core-seconds of oracle work on the all-core sample
+    defaults = {"batched": (256, 32), "single_cadence": (32, 4), "differentiated": (32, 4), "tiny": (1, 1)}
     n_all, n_one = defaults.get(args.workload, (8, 1))
     n_all = min(args.cpu_channels or n_all, C)
     n_one = min(args.cpu_channels_1t or n_one, C)
