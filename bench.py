@@ -381,7 +381,10 @@ TRAFFIC_SUMMARY = {"single_cadence": "k_tile_fused_single_cadence_traffic.json",
 
 
 def fused_kernel_name(W, info):
-    block = 128 if info["tile"] <= 32 and W + 1 <= 8 else 256
+    if W + 1 <= 8:
+        block = 128 if info["tile"] <= 32 else 512
+    else:
+        block = 256
     return f"k_tile<{W + 1}, {info['seg_max']}, 2, {block}, 4> (fused)"
 
 

@@ -52,8 +52,22 @@ __device__ __forceinline__ float quad_xor2(float v) {
 
 // One (channel, tile) of the work: zero the accumulator, walk the tile's work
 // list, write the tile.  tabE must already hold the extended kernel table.
+// 512-thread workgroups (64-cell tiles) take the tile's listings in batches of
+// kSortBatch and visit each batch sorted by the 16 x 16-cell block that holds the
+// window centre (a counting sort in LDS), so that the quads of a wave read
+// overlapping G_in windows and share their cache lines.
+constexpr int kSortBatch = 1024;
+#ifndef RTS_SORT_SIDE
+#define RTS_SORT_SIDE 8
+#endif
+constexpr int kSortSide = RTS_SORT_SIDE;              // bins per tile edge
+constexpr int kSortBins = kSortSide * kSortSide;
+template <int BLOCK>
+constexpr bool tile_sorts() { return BLOCK == 512; }
+
 template <int WN, int SMAX, int MODE, int BLOCK, int GROUP>
-__device__ __forceinline__ void tile_body(const TileArgs &a, const int key, const float *tabE, double *acc) {
+__device__ __forceinline__ void tile_body(const TileArgs &a, const int key, const float *tabE, double *acc,
+                                          uint2 *sorted) {
   // GROUP (= 4) lanes share a segment; each owns CPL window columns.
   static_assert(GROUP == 4, "the DPP reductions and the quad layout assume four lanes per segment");
   constexpr int kGroup = GROUP;
@@ -79,12 +93,56 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
   double chi2 = 0.0;
 
   constexpr uint32_t kStride = BLOCK / kGroup;
-  uint32_t k = beg + threadIdx.x / kGroup;
+  constexpr bool kSort = tile_sorts<BLOCK>();
+  __shared__ uint32_t sort_cnt[kSortBins];
+  for (uint32_t bb = beg;; bb += kSortBatch) {
+  uint32_t lo = beg, hi = end;
+  if constexpr (kSort) {
+    if (bb >= end) break;
+    const int nb = (int)min((uint32_t)kSortBatch, end - bb);
+    if (threadIdx.x < kSortBins) sort_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    constexpr int kPer = kSortBatch / BLOCK;
+    uint2 r[kPer];
+    int bin[kPer];
+    uint32_t pos[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+      const int j = (int)threadIdx.x + m * BLOCK;
+      bin[m] = -1;
+      if (j < nb) {
+        r[m] = a.list[bb + j];
+        const int cx = (int)(r[m].y & kRecXMask) - x0 + WN / 2;
+        const int cy = (int)((r[m].y >> kRecYShift) & kRecXMask) - y0 + WN / 2;
+        const int bx = min(max(cx, 0) * kSortSide / T, kSortSide - 1);
+        const int by = min(max(cy, 0) * kSortSide / T, kSortSide - 1);
+        bin[m] = by * kSortSide + bx;
+        pos[m] = atomicAdd(&sort_cnt[bin[m]], 1u);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t run = 0;
+      for (int b = 0; b < kSortBins; ++b) {
+        const uint32_t n = sort_cnt[b];
+        sort_cnt[b] = run;
+        run += n;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kPer; ++m)
+      if (bin[m] >= 0) sorted[sort_cnt[bin[m]] + pos[m]] = r[m];
+    __syncthreads();
+    lo = 0;
+    hi = (uint32_t)nb;
+  }
+  uint32_t k = lo + threadIdx.x / kGroup;
   uint2 rec_next = make_uint2(0u, 0u);
-  if (k < end) rec_next = a.list[k];
-  for (; k < end; k += kStride) {
+  if (k < hi) rec_next = kSort ? sorted[k] : a.list[k];
+  for (; k < hi; k += kStride) {
     const uint2 rec = rec_next;
-    if (k + kStride < end) rec_next = a.list[k + kStride];   // prefetch the next record
+    if (k + kStride < hi) rec_next = kSort ? sorted[k + kStride] : a.list[k + kStride];   // prefetch the next record
     const bool home = (rec.y >> kRecHomeBit) & 1u;
     if (MODE == kDegrid && !home) continue;
     const int X0 = (int)(rec.y & kRecXMask);
@@ -333,6 +391,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     }
   }
 
+  if constexpr (!kSort) break;
+  __syncthreads();   // the next batch overwrites the sorted listings
+  }
+
   if (MODE == kFused) {
     __shared__ double red[BLOCK / 64];
     for (int o = 32; o > 0; o >>= 1) chi2 += __shfl_down(chi2, o, 64);
@@ -363,14 +425,16 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
   __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK != 256 ? RTS_TILE_WAVES : 2)))
 
 // Shared-memory layout of both launches: the extended kernel table, then the FP64
-// accumulator [tile][tile][2] (kGrid, kFused).  LDS float atomics are an order of
+// accumulator [tile][tile][2] (kGrid, kFused), then (512-thread workgroups) the
+// sorted batch of listings.  LDS float atomics are an order of
 // magnitude slower than FP64 ones on this GPU; FP64 also keeps the tile sums
 // nearly independent of the order the work list is visited in.
-template <int BLOCK>
-__device__ __forceinline__ float *load_table(const TileArgs &a, double *&acc) {
+template <int BLOCK, int MODE>
+__device__ __forceinline__ float *load_table(const TileArgs &a, double *&acc, uint2 *&sorted) {
   extern __shared__ float4 smem4[];
   float *tabE = reinterpret_cast<float *>(smem4);     // [2*OS][WNP], rows 16-byte aligned
   acc = reinterpret_cast<double *>(tabE + a.OS2 * a.WNP);
+  sorted = reinterpret_cast<uint2 *>(acc + (MODE != kDegrid ? 2 * a.tile * a.tile : 0));
   for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += BLOCK) tabE[i] = a.tabE[i];
   __syncthreads();
   return tabE;
@@ -380,8 +444,9 @@ __device__ __forceinline__ float *load_table(const TileArgs &a, double *&acc) {
 template <int WN, int SMAX, int MODE, int BLOCK, int GROUP>
 __global__ RTS_TILE_ATTRS(BLOCK, GROUP) void k_tile(TileArgs a) {
   double *acc;
-  const float *tabE = load_table<BLOCK>(a, acc);
-  tile_body<WN, SMAX, MODE, BLOCK, GROUP>(a, xcd_remap(blockIdx.x, gridDim.x), tabE, acc);
+  uint2 *sorted;
+  const float *tabE = load_table<BLOCK, MODE>(a, acc, sorted);
+  tile_body<WN, SMAX, MODE, BLOCK, GROUP>(a, xcd_remap(blockIdx.x, gridDim.x), tabE, acc, sorted);
 }
 
 // Persistent launch: a few workgroups per CU pull tiles from eight queues, one
@@ -391,7 +456,8 @@ __global__ RTS_TILE_ATTRS(BLOCK, GROUP) void k_tile(TileArgs a) {
 template <int WN, int SMAX, int MODE, int BLOCK, int GROUP>
 __global__ RTS_TILE_ATTRS(BLOCK, GROUP) void k_tile_persistent(TileArgs a) {
   double *acc;
-  const float *tabE = load_table<BLOCK>(a, acc);
+  uint2 *sorted;
+  const float *tabE = load_table<BLOCK, MODE>(a, acc, sorted);
   __shared__ int item;
   const int per = (a.nkeys + 7) / 8;
   for (int k = 0; k < 8; ++k) {
@@ -403,7 +469,7 @@ __global__ RTS_TILE_ATTRS(BLOCK, GROUP) void k_tile_persistent(TileArgs a) {
       const int it = item;
       __syncthreads();
       if (it >= qlen) break;
-      tile_body<WN, SMAX, MODE, BLOCK, GROUP>(a, (int)a.order[qi * per + it], tabE, acc);
+      tile_body<WN, SMAX, MODE, BLOCK, GROUP>(a, (int)a.order[qi * per + it], tabE, acc, sorted);
     }
   }
 }
