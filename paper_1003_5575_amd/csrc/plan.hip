@@ -750,10 +750,13 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
   __syncthreads();
   const int64_t ntr = (int64_t)a.ncopy * a.B;
   const int64_t tr_end = min(ntr, (int64_t)bx * a.chunk + a.chunk);
-  for (int64_t tr = (int64_t)bx * a.chunk + threadIdx.x; tr < tr_end; tr += kBlock) {
-    const int copy = (int)(tr / a.B);
-    const int b = (int)(tr - (int64_t)copy * a.B);
-    for (int c = c0; c < c1; ++c) {
+  // Channels outermost: the records one workgroup writes for a key form one
+  // contiguous run of the work list, and visiting one channel's keys at a time
+  // writes each run within a short interval (whole cache lines in L2).
+  for (int c = c0; c < c1; ++c) {
+    for (int64_t tr = (int64_t)bx * a.chunk + threadIdx.x; tr < tr_end; tr += kBlock) {
+      const int copy = (int)(tr / a.B);
+      const int b = (int)(tr - (int64_t)copy * a.B);
       auto emit = [&](const Seg &seg) {
         for_listings(a, c, copy, seg, [&](int64_t key, int, int, bool home) {
           const uint32_t pos = atomicAdd(&bins[(int)(key - (int64_t)c0 * a.nT2)], 1u);

@@ -244,7 +244,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     float kyn[KYN], kxn[CPL];
     auto read_rows = [&](const uint32_t cw, float (&ky)[KYN], float (&kx)[CPL]) {
       const int sx = cw & 0x7F, sy = (cw >> 7) & 0x7F;
-      const float4 *ry = reinterpret_cast<const float4 *>(tabE + sy * a.WNP);
+      const float4 *ry = reinterpret_cast<const float4 *>(tabE + sy * KYN);   // KYN == WNP, the row stride
 #pragma unroll
       for (int j4 = 0; j4 < KYN / 4; ++j4) {
         const float4 t4 = ry[j4];
@@ -253,7 +253,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         ky[4 * j4 + 2] = t4.z;
         ky[4 * j4 + 3] = t4.w;
       }
-      const float *rx = tabE + sx * a.WNP + col0;
+      const float *rx = tabE + sx * KYN + col0;
       if (CPL == 2 && kFullCols) {
         const float2 t2 = *reinterpret_cast<const float2 *>(rx);
         kx[0] = t2.x;
