@@ -262,7 +262,10 @@ rts_status rts_plan_valid_mask(rts_plan_t plan, uint8_t *mask, void *stream);
  * separable grid correction, khat the Fourier transform of the plan's
  * Kaiser-Bessel window and nu = (q - N/2) / N for pixel q (pixel N/2 is l = 0).
  * grid and image_out: complex64 [C][N][N] device buffers, 16-byte aligned,
- * caller-owned; they may be the same buffer (in place).  The first call builds
+ * caller-owned; they may be the same buffer (in place), which with N a multiple
+ * of 4 saves one pass over the grids (the grid is transformed as it is and one
+ * pass exchanges the quadrants while applying sign and correction; out of place a
+ * sign pass copies the modulated grid into image_out first).  The first call builds
  * the plan's FFT plan (batched over channels) and correction table, which
  * allocates device memory and copies the table synchronously; later calls
  * allocate nothing and are asynchronous on `stream`.

@@ -3,9 +3,14 @@
 // centred inverse 2-D FFT of the grid divided by the separable grid correction
 // khat(nu_x) khat(nu_y), nu = (q - N/2) / N, where khat is the Fourier transform
 // of the gridding kernel.  For even N the centring shifts are folded into sign
-// factors: with s(x, y) = (-1)^(x+y), shift(IFFT(shift(G))) = s . IFFT(s . G).
+// factors: with s(x, y) = (-1)^(x+y), shift(IFFT(shift(G))) = s . IFFT(s . G)
+// = s . shift(IFFT(G)).
 // The FFT itself is hipFFT's batched in-place transform (all channels in one
-// call); the sign and correction passes are the kernels below.
+// call); the sign and correction passes are the kernels below.  Out of place,
+// the sign pass copies s . G into the output, which is then transformed in place
+// and corrected.  In place (image over the grid, N a multiple of 4), the grid is
+// transformed as it is and one pass swaps the quadrants while it applies the
+// sign and the correction, so the image costs one full-grid pass less.
 #include <hipfft/hipfft.h>
 
 #include <cmath>
@@ -53,6 +58,32 @@ __global__ __launch_bounds__(kBlock) void k_image_post(float4 *img, const float 
   const float f0 = sy * rc[x], f1 = -sy * rc[x + 1];
   const float4 v = img[i];
   img[i] = make_float4(f0 * v.x, f0 * v.y, f1 * v.z, f1 * v.w);
+}
+
+// In place, after the transform of the unmodulated grid (F = IFFT(G)):
+// img(p) = s(p) F(p') / (khat khat)(p) with p' = p + (N/2, N/2) mod N, the
+// centring shift.  The map p -> p' pairs pixels of the upper and lower halves, so
+// each thread reads both members of two such pairs (pixels x, x+1 of row y < N/2
+// and pixels x', x'+1 of row y + N/2, x' = (x + N/2) mod N) and writes them
+// exchanged.  s(p') = s(p) since N is even; x' is even since N/2 is.
+__global__ __launch_bounds__(kBlock) void k_image_swap(float4 *img, const float *rc, int64_t nquads, int N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nquads) return;
+  const int h = N / 2;
+  const int64_t per_c = (int64_t)h * h;   // threads per channel: N/2 rows x N/2 pixel pairs
+  const int64_t c = i / per_c;
+  const int rem = (int)(i - c * per_c);
+  const int y = rem / h, x = 2 * (rem - y * h);
+  const int x2 = (x + h) % N, y2 = y + h;
+  float4 *plane = img + c * ((int64_t)N * N / 2);
+  const int64_t ia = ((int64_t)y * N + x) / 2, ib = ((int64_t)y2 * N + x2) / 2;
+  const float4 a = plane[ia], b = plane[ib];
+  const float s0 = ((x + y) & 1) ? -1.0f : 1.0f;
+  const float fa = s0 * rc[y], fb = s0 * rc[y2];
+  const float a0 = fa * rc[x], a1 = -fa * rc[x + 1];
+  const float b0 = fb * rc[x2], b1 = -fb * rc[x2 + 1];
+  plane[ia] = make_float4(a0 * b.x, a0 * b.y, a1 * b.z, a1 * b.w);
+  plane[ib] = make_float4(b0 * a.x, b0 * a.y, b1 * a.z, b1 * a.w);
 }
 
 const char *fft_error(hipfftResult r) {
@@ -121,12 +152,16 @@ extern "C" rts_status rts_image(rts_plan_t plan, const float *grid, float *image
   hipStream_t s = (hipStream_t)stream;
   const int64_t npairs = (int64_t)P.C * P.N * P.N / 2;
   const unsigned nb = (unsigned)((npairs + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_image_pre, dim3(nb), dim3(kBlock), 0, s, (const float4 *)grid, (float4 *)image_out, npairs,
-                     P.N);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) {
-    set_error("imager sign pass: %s", hipGetErrorString(e));
-    return RTS_E_HIP;
+  const bool swap = (const float *)image_out == grid && P.N % 4 == 0;
+  hipError_t e = hipSuccess;
+  if (!swap) {
+    hipLaunchKernelGGL(k_image_pre, dim3(nb), dim3(kBlock), 0, s, (const float4 *)grid, (float4 *)image_out, npairs,
+                       P.N);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error("imager sign pass: %s", hipGetErrorString(e));
+      return RTS_E_HIP;
+    }
   }
   hipfftHandle h = (hipfftHandle)P.fft;
   hipfftResult r = hipfftSetStream(h, s);
@@ -136,8 +171,15 @@ extern "C" rts_status rts_image(rts_plan_t plan, const float *grid, float *image
     set_error("hipfftExecC2C: %s", fft_error(r));
     return RTS_E_HIP;
   }
-  hipLaunchKernelGGL(k_image_post, dim3(nb), dim3(kBlock), 0, s, (float4 *)image_out, (const float *)P.d_rcorr,
-                     npairs, P.N);
+  if (swap) {
+    const int64_t nquads = npairs / 2;
+    const unsigned nq = (unsigned)((nquads + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_image_swap, dim3(nq), dim3(kBlock), 0, s, (float4 *)image_out, (const float *)P.d_rcorr,
+                       nquads, P.N);
+  } else {
+    hipLaunchKernelGGL(k_image_post, dim3(nb), dim3(kBlock), 0, s, (float4 *)image_out, (const float *)P.d_rcorr,
+                       npairs, P.N);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) {
     set_error("imager correction pass: %s", hipGetErrorString(e));

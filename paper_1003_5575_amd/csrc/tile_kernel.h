@@ -159,9 +159,21 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     }
     const size_t ci = vi + (size_t)(c * (a.ncopy - 1) + copy) * copy_stride;
 
-    // Issue every global load of the segment before any arithmetic: the packed
-    // coordinates, visibilities and weights of all its samples and this lane's
-    // columns of the G_in window.
+    // Issue every global load of the segment before any arithmetic: this lane's
+    // columns of the G_in window first (their addresses need only the listing
+    // record), then the packed coordinates, visibilities and weights of all its
+    // samples, so that the segment waits for one memory round trip.
+    float2 gw[WN][CPL];
+    if (MODE != kGrid) {
+      const float2 *g = a.gin + ((size_t)c * a.N + Y0) * a.N + X0 + col0;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+#pragma unroll
+        for (int i = 0; i < CPL; ++i)
+          gw[j][i] = (kFullCols || col0 + i < WN) ? g[i] : make_float2(0.0f, 0.0f);
+        g += a.N;
+      }
+    }
     uint32_t cws[SMAX];
     float2 vs[SMAX];
     float ws[SMAX];
@@ -208,17 +220,6 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
             ws[s] = a.w[vi + s];
           }
         }
-      }
-    }
-    float2 gw[WN][CPL];
-    if (MODE != kGrid) {
-      const float2 *g = a.gin + ((size_t)c * a.N + Y0) * a.N + X0 + col0;
-#pragma unroll
-      for (int j = 0; j < WN; ++j) {
-#pragma unroll
-        for (int i = 0; i < CPL; ++i)
-          gw[j][i] = (kFullCols || col0 + i < WN) ? g[i] : make_float2(0.0f, 0.0f);
-        g += a.N;
       }
     }
     float2 up[WN][CPL];
