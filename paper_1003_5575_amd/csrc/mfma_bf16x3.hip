@@ -49,7 +49,14 @@ typedef unsigned u2_t __attribute__((ext_vector_type(2)));
 typedef unsigned u4w_t __attribute__((ext_vector_type(4), aligned(4)));   // 16 bytes, word-aligned
 
 constexpr int kMT = 16;          // subtile edge (one MFMA output block)
-constexpr int kQueue = 128;      // listing queue per wave (at most chunk - 1 + 64 entries)
+// Listing queue per wave: at most per_chunk - 1 + 64 entries, per_chunk = staged
+// slots / seg_max <= 64 / 2 (seg_max is 2, 4 or 8).
+constexpr int kQueue = 96;
+// Sample slots staged at once (one per lane, feeding several MFMA steps): 64 with
+// regions of two subtiles (8 waves), 32 with one (up to 16 waves), which keeps
+// the widest padded tables within 64 KiB of LDS.
+template <int NR>
+constexpr int stage_slots() { return NR == 2 ? 64 : 32; }
 
 // Waves per workgroup: one per region; regions of two subtiles when the tile
 // edge is a multiple of 32 (at most 64 / 32 * 64 / 16 = 8), else one subtile
@@ -232,7 +239,8 @@ __global__ __launch_bounds__(64 * max_waves<GR>()) __attribute__((amdgpu_waves_p
 void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_lo, PbTables pb) {
   constexpr int kChunk = 32;                         // sample slots per MFMA K step
   constexpr int RH = GR * kMT, RW = kMT;
-  __shared__ uint4 slots[max_waves<GR>()][kChunk];
+  constexpr int kStage = stage_slots<GR>();
+  __shared__ uint4 slots[max_waves<GR>()][kStage];
   __shared__ uint2 queue[max_waves<GR>()][kQueue];
   const int key = tile_key(a);
   if (key < 0) return;
@@ -266,56 +274,17 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
   // listing of its segment.
   double chi2 = 0.0;
 
-  for_subtile_chunks(a, beg, end, x0, y0, RW, RH, true, q, kChunk >> lg, [&](int n) {
-    // Stage the chunk: slot lane holds sample (lane mod seg_max) of queued record lane / seg_max.
-    if (lane < kChunk) {
-      uint4 sl = make_uint4(empty_ya, empty_xa, 0u, 0u);
-      const int li = lane >> lg;
-      const int j = lane & (a.seg_max - 1);
-      if (li < n) {
-        const uint2 rec = q[li];
-        const int nt = (int)((rec.y >> kRecNtShift) & 7u) + 1;
-        if (j < nt) {
-          const int copy = (int)((rec.y >> kRecCopyBit) & 1u);
-          const size_t vi = rec.x + j;
-          const size_t ci = vi + (size_t)(c * (a.ncopy - 1) + copy) * copy_stride;
-          const uint16_t cw = a.coords[ci];
-          float2 v = a.vis[vi];
-          const float wt = a.w[vi];
-          if (RES) {                                 // the fused step grids w (V - M)
-            const float2 m = a.model[vi];
-            v.x -= m.x;
-            v.y -= m.y;
-            const int dx0 = (int)(rec.y & kRecXMask) - x0;
-            const int dy0 = (int)((rec.y >> kRecYShift) & kRecXMask) - y0;
-            const bool mine = ((rec.y >> kRecHomeBit) & 1u) && copy == 0 && (unsigned)dx0 < (unsigned)RW &&
-                              (unsigned)dy0 < (unsigned)RH && (cw & kCoordValid);
-            if (mine) chi2 += (double)(wt * fmaf(v.x, v.x, v.y * v.y));
-          }
-          uint32_t ya, xa;
-          if (PB)
-            slot_offsets_pb(a, pb, (uint32_t)vi, rec.y, cw, x0, y0, ya, xa);
-          else
-            slot_addresses(a, pg, RH, RW, rec.y, cw, x0, y0, ya, xa);
-          const bool ok = (cw & kCoordValid) != 0;
-          sl.x = ok ? ya : empty_ya;
-          sl.y = ok ? xa : empty_xa;
-          sl.z = ok ? __float_as_uint(wt * v.x) : 0u;
-          sl.w = ok ? __float_as_uint(copy ? -(wt * v.y) : wt * v.y) : 0u;
-        }
-      }
-      ss[lane] = sl;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
-
+  // Contraction of nsteps K steps of staged slots.
+  auto contract = [&](const uint4 *sb, int nsteps) {
+    for (int ks = 0; ks < nsteps; ++ks) {
+    const uint4 *sk = sb + kChunk * ks;
     if constexpr (F32) {
       // FP32 operands, one v_mfma_f32_16x16x4_f32 per term, row block and step of
       // 4 samples s = 4 st + g: A_rb[y][g] = ky_s(y0 + 16 rb + y) in lane y + 16g,
       // B[g][x] = a_s kx_s(x0 + x) in lane x + 16g.
 #pragma unroll
       for (int st = 0; st < kChunk / 4; ++st) {
-        const uint4 sl = ss[4 * st + g];
+        const uint4 sl = sk[4 * st + g];
         float av[GR], kx;
         if (PB) {
 #pragma unroll
@@ -343,7 +312,7 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
         float kx[2], ar[2], ai[2];
   #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const uint4 sl = ss[8 * g + 2 * p + h];
+          const uint4 sl = sk[8 * g + 2 * p + h];
           if (PB) {
             const uint32_t ya = sl.x + i16, xa = sl.y + i16;
   #pragma unroll
@@ -384,6 +353,52 @@ void k_grid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi, const uint16_t *tab_
         acc_im[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bih, acc_im[rb], 0, 0, 0);
       }
     }
+    }
+  };
+  for_subtile_chunks(a, beg, end, x0, y0, RW, RH, true, q, kStage >> lg, [&](int n) {
+    // Stage kStage slots, one per lane: slot lane holds sample (lane mod seg_max)
+    // of queued record lane / seg_max.  They feed up to kStage / 32 K steps.
+    if (kStage == 64 || lane < kStage) {
+      uint4 sl = make_uint4(empty_ya, empty_xa, 0u, 0u);
+      const int li = lane >> lg;
+      const int j = lane & (a.seg_max - 1);
+      if (li < n) {
+        const uint2 rec = q[li];
+        const int nt = (int)((rec.y >> kRecNtShift) & 7u) + 1;
+        if (j < nt) {
+          const int copy = (int)((rec.y >> kRecCopyBit) & 1u);
+          const size_t vi = rec.x + j;
+          const size_t ci = vi + (size_t)(c * (a.ncopy - 1) + copy) * copy_stride;
+          const uint16_t cw = a.coords[ci];
+          float2 v = a.vis[vi];
+          const float wt = a.w[vi];
+          if (RES) {                                 // the fused step grids w (V - M)
+            const float2 m = a.model[vi];
+            v.x -= m.x;
+            v.y -= m.y;
+            const int dx0 = (int)(rec.y & kRecXMask) - x0;
+            const int dy0 = (int)((rec.y >> kRecYShift) & kRecXMask) - y0;
+            const bool mine = ((rec.y >> kRecHomeBit) & 1u) && copy == 0 && (unsigned)dx0 < (unsigned)RW &&
+                              (unsigned)dy0 < (unsigned)RH && (cw & kCoordValid);
+            if (mine) chi2 += (double)(wt * fmaf(v.x, v.x, v.y * v.y));
+          }
+          uint32_t ya, xa;
+          if (PB)
+            slot_offsets_pb(a, pb, (uint32_t)vi, rec.y, cw, x0, y0, ya, xa);
+          else
+            slot_addresses(a, pg, RH, RW, rec.y, cw, x0, y0, ya, xa);
+          const bool ok = (cw & kCoordValid) != 0;
+          sl.x = ok ? ya : empty_ya;
+          sl.y = ok ? xa : empty_xa;
+          sl.z = ok ? __float_as_uint(wt * v.x) : 0u;
+          sl.w = ok ? __float_as_uint(copy ? -(wt * v.y) : wt * v.y) : 0u;
+        }
+      }
+      ss[lane] = sl;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
+    contract(ss, (n << lg) > kChunk ? 2 : 1);   // the second K step only when its slots hold samples
     __builtin_amdgcn_wave_barrier();   // the next chunk's slot writes follow these reads
   });
 
@@ -438,9 +453,10 @@ __device__ __forceinline__ float dpp_xor1(float v) {
 template <int DC, bool PB, bool F32>
 __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(TileArgs a, const uint16_t *tab_hi,
                                                                              const uint16_t *tab_lo, PbTables pb) {
-  constexpr int kChunk = 16;
+  constexpr int kChunk = 16;                         // samples per MFMA step (its rows)
   constexpr int RH = kMT, RW = DC * kMT;
-  __shared__ uint4 dslots[max_waves<DC>()][kChunk];
+  constexpr int kStage = stage_slots<DC>();
+  __shared__ uint4 dslots[max_waves<DC>()][kStage];
   __shared__ uint2 queue[max_waves<DC>()][kQueue];
   const int key = tile_key(a);
   if (key < 0) return;
@@ -495,9 +511,10 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
   const int lg = __builtin_ctz((unsigned)a.seg_max);
   const int b3 = (i16 >> 3) & 1, b2 = (i16 >> 2) & 1, b1 = (i16 >> 1) & 1;
 
-  for_subtile_chunks(a, beg, end, x0, y0, RW, RH, false, q, kChunk >> lg, [&](int n) {
-    // Stage 16 sample slots: slot j holds sample (j mod seg_max) of queued record j / seg_max.
-    if (lane < kChunk) {
+  for_subtile_chunks(a, beg, end, x0, y0, RW, RH, false, q, kStage >> lg, [&](int n) {
+    // Stage kStage sample slots, one per lane: slot j holds sample (j mod seg_max)
+    // of queued record j / seg_max.  They feed up to kStage / 16 steps of 16 samples.
+    if (kStage == 64 || lane < kStage) {
       uint4 sl = make_uint4(empty_ya, empty_xa, 0xFFFFFFFFu, 0u);
       const int li = lane >> lg;
       const int j = lane & (a.seg_max - 1);
@@ -523,6 +540,9 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the slot writes are visible to the wave
 
+    const int nsteps = ((n << lg) + kChunk - 1) / kChunk;   // steps holding samples (wave-uniform)
+    for (int ks = 0; ks < nsteps; ++ks) {
+    const uint4 *dk = ds + kChunk * ks;
     // Column weights of the samples 4g + r whose H rows this lane receives.  From
     // device memory (per-baseline tables), or ahead of the longer FP32-operand
     // contraction, they are read before it so that the reads overlap it; for the
@@ -532,7 +552,7 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     auto column_weights = [&]() {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const uint4 sl = ds[4 * g + r];
+        const uint4 sl = dk[4 * g + r];
 #pragma unroll
         for (int cb = 0; cb < DC; ++cb)
           kxv[r][cb] = PB ? pb.tab[sl.y + i16 + kMT * cb] : lds_f32(lds, sl.y + 4u * i16 + 4u * kMT * cb);
@@ -543,7 +563,7 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     f4_t hr[DC], hi[DC];
     if constexpr (F32) {
       // FP32: K step t covers region rows 4t + g; A[s][g] = k_y of sample s = i16.
-      const uint32_t ya = ds[i16].x;
+      const uint32_t ya = dk[i16].x;
 #pragma unroll
       for (int cb = 0; cb < DC; ++cb) hr[cb] = hi[cb] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -562,13 +582,13 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
         uint32_t t0, t1, t2, t3;
         if (PB) {
           // four consecutive words at any word offset: a 16-byte load with 4-byte alignment
-          const u4w_t t = *reinterpret_cast<const u4w_t *>(pb.thl + ds[i16].x + 4u * g);
+          const u4w_t t = *reinterpret_cast<const u4w_t *>(pb.thl + dk[i16].x + 4u * g);
           t0 = t[0];
           t1 = t[1];
           t2 = t[2];
           t3 = t[3];
         } else {
-          const uint32_t ya = ds[i16].x + 16u * g;
+          const uint32_t ya = dk[i16].x + 16u * g;
           t0 = lds_u32(lds, ya);
           t1 = lds_u32(lds, ya + 4u);
           t2 = lds_u32(lds, ya + 8u);
@@ -621,6 +641,7 @@ __global__ __launch_bounds__(64 * max_waves<DC>()) void k_degrid_mfma_bf16x3(Til
     z += dpp_xor1(z);
     const uint32_t vi = b3 ? (b2 ? vis_r[3] : vis_r[2]) : (b2 ? vis_r[1] : vis_r[0]);
     if (!(i16 & 1) && vi != 0xFFFFFFFFu) atomicAdd(reinterpret_cast<float *>(a.model) + 2 * (size_t)vi + b1, z);
+    }
     __builtin_amdgcn_wave_barrier();   // the next chunk's slot writes follow these reads
   });
 }
@@ -663,8 +684,9 @@ __global__ void k_build_pb_tables(const float *__restrict__ tab, int64_t total, 
 size_t mfma_lds_bytes(int WN, int OS2, int tile) {
   const int pair = tile % (2 * kMT) == 0 ? 2 : 1;
   const size_t waves = (size_t)max_waves<1>();
-  const size_t grid_static = pair == 2 ? (size_t)max_waves<2>() * (32 * 16 + kQueue * 8) : waves * (32 * 16 + kQueue * 8);
-  const size_t degrid_static = pair == 2 ? (size_t)max_waves<2>() * (16 * 16 + kQueue * 8) : waves * (16 * 16 + kQueue * 8);
+  const size_t grid_static = pair == 2 ? (size_t)max_waves<2>() * (stage_slots<2>() * 16 + kQueue * 8)
+                                       : waves * (stage_slots<1>() * 16 + kQueue * 8);
+  const size_t degrid_static = grid_static;
   const PadGeom g = pad_geom(WN, OS2, pair * kMT, kMT), d = pad_geom(WN, OS2, kMT, pair * kMT);
   const size_t gl = grid_static + (size_t)16 * ((g.TX + g.TA + 3) / 4);
   const size_t dl = degrid_static + (size_t)16 * ((d.TX + d.TA + 3) / 4);
