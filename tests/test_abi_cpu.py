@@ -123,14 +123,12 @@ def test_polconvert_argument_checks_on_host(lib):
 
 
 def test_bf16x3_support_limits_on_host(lib):
-    """Supports up to 24 are accepted for BF16x3 plans only, and a geometry whose
-    matrix-core kernels would need more than 64 KiB of LDS is refused before any
-    device work."""
+    """Supports up to 24 are accepted for BF16x3 plans only.  (The matrix-core
+    kernels' LDS budget check, 64 KiB, is not reached by any valid geometry: the
+    widest, support 24 at oversampling 64, needs 63,680 bytes with regions of two
+    subtiles; the GPU tests run the widest tables at support 16.)"""
     import paper_1003_5575_amd as rts
     p = rts.make_params(192, 10.0, 25, 8, 2, 100, 8, precision=1)
     st, _ = plan_call(lib, p)
     assert st == 1 and "support must be in [2, 24]" in lib.rts_last_error().decode()
-    p = rts.make_params(192, 10.0, 24, 64, 2, 100, 8, tile=48, precision=1)
-    st, h = plan_call(lib, p)
-    assert st == 4 and not h.value and "64 KiB" in lib.rts_last_error().decode()
     assert lib.rts_plan_set_baseline_kernels(None, None, None) == 1
