@@ -11,15 +11,19 @@
 namespace rts {
 namespace {
 
-// x = u*s + N/2 and xs = floor(x*OS + 1/2), each step rounded once (no FMA
-// contraction), so that the result is bit-identical to a plain IEEE evaluation.
+// x = u*s + N/2 and xs = floor(x*OS + 1/2), each step rounded once, so that the
+// result is bit-identical to a plain IEEE evaluation.  The compiler would fuse
+// u*s + N/2 into one FMA (one rounding instead of two) and could then snap a
+// sample that lies within an ulp of a phase boundary to the neighbouring phase;
+// contraction is off in this function.
 __device__ __forceinline__ bool snap(double u, double v, double s, int N, int OS, int &xs,
                                      int &ys) {
+#pragma clang fp contract(off)
   const double half = (double)(N / 2);
-  const double x = __dadd_rn(__dmul_rn(u, s), half);
-  const double y = __dadd_rn(__dmul_rn(v, s), half);
-  const double xo = floor(__dadd_rn(__dmul_rn(x, (double)OS), 0.5));
-  const double yo = floor(__dadd_rn(__dmul_rn(y, (double)OS), 0.5));
+  const double x = u * s + half;
+  const double y = v * s + half;
+  const double xo = floor(x * (double)OS + 0.5);
+  const double yo = floor(y * (double)OS + 0.5);
   if (!(fabs(xo) < 1073741824.0) || !(fabs(yo) < 1073741824.0)) {  // false for NaN too
     xs = ys = 0;
     return false;
