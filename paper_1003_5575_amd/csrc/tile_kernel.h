@@ -222,13 +222,8 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         }
       }
     }
+    // The accumulated update: sample 0 (every segment has one) initialises it.
     float2 up[WN][CPL];
-    if (MODE != kDegrid) {
-#pragma unroll
-      for (int j = 0; j < WN; ++j)
-#pragma unroll
-        for (int i = 0; i < CPL; ++i) up[j][i] = make_float2(0.0f, 0.0f);
-    }
 
     float chi2_seg = 0.0f;   // this segment's sum of w |r|^2 (SMAX terms, FP32)
     // With the 256-register budget the segment's model values are kept and
@@ -312,7 +307,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         mv[s] = ok ? m : make_float2(0.0f, 0.0f);
         if (!kBufModel && put_model && q == 0 && s < nt) a.model[vi + s] = mv[s];
       }
-      if (MODE != kDegrid && (kAhead || ok)) {
+      if (MODE != kDegrid && (kAhead || ok || s == 0)) {
         float2 v = vs[s];
         const float wt = ws[s];
         if (copy) v.y = -v.y;
@@ -334,8 +329,12 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
           const float br = ar * kx[i], bi = ai * kx[i];
 #pragma unroll
           for (int j = 0; j < WN; ++j) {
-            up[j][i].x = fmaf(br, ky[j], up[j][i].x);
-            up[j][i].y = fmaf(bi, ky[j], up[j][i].y);
+            if (s == 0) {
+              up[j][i] = make_float2(br * ky[j], bi * ky[j]);
+            } else {
+              up[j][i].x = fmaf(br, ky[j], up[j][i].x);
+              up[j][i].y = fmaf(bi, ky[j], up[j][i].y);
+            }
           }
         }
       }
@@ -357,12 +356,14 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
       }
     }
     if (MODE != kDegrid) {
-      // Add this lane's window columns to the tile accumulator.  Windows entirely
-      // inside the tile (most of them) skip the per-cell bounds checks.
+      // Add this lane's window columns to the tile accumulator.  A wave whose
+      // windows all lie inside the tile (most waves) skips the per-cell bounds
+      // checks; a wave with any window across a tile edge takes the checked form
+      // for all of its segments (one path per wave instead of both).
       const int lx = X0 + col0 - x0, ly = Y0 - y0;
       const bool inside = T >= WN && (unsigned)(X0 - x0) <= (unsigned)(T - WN) && (unsigned)ly <= (unsigned)(T - WN);
       double *row = acc + 2 * (ly * T + lx);      // dereferenced only inside the tile
-      if (inside) {
+      if (__all(inside)) {
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
 #pragma unroll
