@@ -95,7 +95,7 @@ typedef struct {
   int32_t oversample;   /* OS: kernel phases per cell, 1 <= OS <= 64                     */
   int32_t n_chan;       /* C >= 1                                                         */
   int32_t n_base;       /* B >= 1                                                         */
-  int32_t n_time;       /* T >= 1; C*B*T*(1+conjugate) < 2^31                            */
+  int32_t n_time;       /* T >= 1; C*B*T*(1+conjugate) < 2^31 and B*T < 2^29            */
   double cell_lambda;   /* du > 0: uv cell size in wavelengths                           */
   double beta;          /* Kaiser-Bessel shape; <= 0 selects 2.34 * W                     */
   int32_t conjugate;    /* 1: also grid conj(w V) at (-u, -v) (rts_grid only)             */

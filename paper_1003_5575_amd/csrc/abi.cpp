@@ -109,6 +109,8 @@ rts_status validate(const rts_params *p) {
               "schedule %d is not available", p->schedule);
   const int64_t n = (int64_t)p->n_chan * p->n_base * p->n_time * (1 + p->conjugate);
   RTS_REQUIRE(n < ((int64_t)1 << 31), "n_chan*n_base*n_time*(1+conjugate) must be < 2^31");
+  // the kernels address one channel's samples with 32-bit byte offsets
+  RTS_REQUIRE((int64_t)p->n_base * p->n_time < ((int64_t)1 << 29), "n_base*n_time must be < 2^29");
   RTS_REQUIRE(p->n_grid >= p->support + 2, "n_grid must be at least support + 2");
   if (mfma_precision(p->precision)) {
     RTS_REQUIRE(p->n_grid % 16 == 0, "matrix-core plans need n_grid divisible by 16");

@@ -25,6 +25,7 @@ namespace rts {
 // kernel: non-temporal stores keep them from displacing G_in windows and sample
 // data in L2.
 typedef float rts_nt_v4f __attribute__((ext_vector_type(4)));
+typedef float rts_v4f_a8 __attribute__((ext_vector_type(4), aligned(8)));   // 16 bytes at an 8-byte boundary
 
 
 // Lanes per segment and window columns per lane.  A group of GROUP adjacent
@@ -48,6 +49,18 @@ __device__ __forceinline__ float quad_xor1(float v) {
 }
 __device__ __forceinline__ float quad_xor2(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+}
+
+// Element i of a per-channel array: a uniform base and a 32-bit byte offset, so
+// the loads take the scalar-base addressing form (no 64-bit address arithmetic
+// per lane).  Per-channel arrays stay below 4 GiB (n_base * n_time < 2^29).
+template <class T>
+__device__ __forceinline__ const T *elem(const T *base, uint32_t i) {
+  return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ T *elem(T *base, uint32_t i) {
+  return reinterpret_cast<T *>(reinterpret_cast<char *>(base) + i * (uint32_t)sizeof(T));
 }
 
 // One (channel, tile) of the work: zero the accumulator, walk the tile's work
@@ -87,7 +100,15 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
 
   const uint32_t cap = (uint32_t)a.list_cap;
   const uint32_t beg = min(a.tile_off[key], cap), end = min(a.tile_off[key + 1], cap);
-  const size_t copy_stride = (size_t)a.B * a.T;
+  // This channel's visibilities, weights, model and packed coordinates ([C][ncopy]
+  // [B][T]), and its G_in plane: listings index them with 32-bit offsets.
+  const uint32_t BT = (uint32_t)a.B * (uint32_t)a.T;
+  const uint32_t vbase = (uint32_t)c * BT;
+  const float2 *vis_c = a.vis + vbase;
+  const float *w_c = a.w + vbase;
+  float2 *model_c = a.model + vbase;
+  const uint16_t *coords_c = a.coords + (size_t)c * a.ncopy * BT;
+  const float2 *gin_c = a.gin + (size_t)c * a.N * a.N;
   const int q = threadIdx.x & (kGroup - 1);       // lane within the group
   const int col0 = q * CPL;                       // first window column of this lane
   double chi2 = 0.0;
@@ -150,14 +171,14 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     const int nt = (int)((rec.y >> kRecNtShift) & 7u) + 1;
     const int copy = (int)((rec.y >> kRecCopyBit) & 1u);
     const bool any = (rec.y >> kRecAnyBit) & 1u;
-    const size_t vi = rec.x;
+    const uint32_t vi = rec.x - vbase;          // first sample, within the channel
     const bool put_model = home && copy == 0 && (MODE == kDegrid || (MODE == kFused && a.write_model));
     if (!any) {
       if (put_model)
-        for (int s = q; s < nt; s += kGroup) a.model[vi + s] = make_float2(0.0f, 0.0f);
+        for (int s = q; s < nt; s += kGroup) *elem(model_c, vi + s) = make_float2(0.0f, 0.0f);
       continue;
     }
-    const size_t ci = vi + (size_t)(c * (a.ncopy - 1) + copy) * copy_stride;
+    const uint32_t ci = vi + (uint32_t)copy * BT;
 
     // Issue every global load of the segment before any arithmetic: this lane's
     // columns of the G_in window first (their addresses need only the listing
@@ -165,13 +186,20 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     // samples, so that the segment waits for one memory round trip.
     float2 gw[WN][CPL];
     if (MODE != kGrid) {
-      const float2 *g = a.gin + ((size_t)c * a.N + Y0) * a.N + X0 + col0;
+      const uint32_t g0 = (uint32_t)(Y0 * a.N + X0 + col0);
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
+        const uint32_t gj = g0 + (uint32_t)(j * a.N);
+        if (CPL == 2 && kFullCols) {
+          // the lane's two columns as one 16-byte load (8-byte aligned)
+          const rts_v4f_a8 t = *reinterpret_cast<const rts_v4f_a8 *>(elem(gin_c, gj));
+          gw[j][0] = make_float2(t.x, t.y);
+          gw[j][CPL - 1] = make_float2(t.z, t.w);
+        } else {
 #pragma unroll
-        for (int i = 0; i < CPL; ++i)
-          gw[j][i] = (kFullCols || col0 + i < WN) ? g[i] : make_float2(0.0f, 0.0f);
-        g += a.N;
+          for (int i = 0; i < CPL; ++i)
+            gw[j][i] = (kFullCols || col0 + i < WN) ? *elem(gin_c, gj + (uint32_t)i) : make_float2(0.0f, 0.0f);
+        }
       }
     }
     uint32_t cws[SMAX];
@@ -182,25 +210,25 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     const bool vec = a.vec && nt == SMAX;
     if (vec) {
       if (SMAX == 8) {
-        const uint4 c4 = *reinterpret_cast<const uint4 *>(a.coords + ci);
+        const uint4 c4 = *reinterpret_cast<const uint4 *>(elem(coords_c, ci));
         cws[0] = c4.x & 0xFFFFu; cws[1 % SMAX] = c4.x >> 16;
         cws[2 % SMAX] = c4.y & 0xFFFFu; cws[3 % SMAX] = c4.y >> 16;
         cws[4 % SMAX] = c4.z & 0xFFFFu; cws[5 % SMAX] = c4.z >> 16;
         cws[6 % SMAX] = c4.w & 0xFFFFu; cws[7 % SMAX] = c4.w >> 16;
       } else {
-        const uint2 c2 = *reinterpret_cast<const uint2 *>(a.coords + ci);
+        const uint2 c2 = *reinterpret_cast<const uint2 *>(elem(coords_c, ci));
         cws[0] = c2.x & 0xFFFFu; cws[1 % SMAX] = c2.x >> 16;
         cws[2 % SMAX] = c2.y & 0xFFFFu; cws[3 % SMAX] = c2.y >> 16;
       }
       if (MODE != kDegrid) {
-        const float4 *v4 = reinterpret_cast<const float4 *>(a.vis + vi);
+        const float4 *v4 = reinterpret_cast<const float4 *>(elem(vis_c, vi));
 #pragma unroll
         for (int h = 0; h < SMAX / 2; ++h) {
           const float4 t4 = v4[h];
           vs[2 * h] = make_float2(t4.x, t4.y);
           vs[2 * h + 1] = make_float2(t4.z, t4.w);
         }
-        const float4 *w4 = reinterpret_cast<const float4 *>(a.w + vi);
+        const float4 *w4 = reinterpret_cast<const float4 *>(elem(w_c, vi));
 #pragma unroll
         for (int h = 0; h < SMAX / 4; ++h) {
           const float4 t4 = w4[h];
@@ -214,10 +242,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         vs[s] = make_float2(0.0f, 0.0f);
         ws[s] = 0.0f;
         if (s < nt) {
-          cws[s] = a.coords[ci + s];
+          cws[s] = *elem(coords_c, ci + s);
           if (MODE != kDegrid) {
-            vs[s] = a.vis[vi + s];
-            ws[s] = a.w[vi + s];
+            vs[s] = *elem(vis_c, vi + s);
+            ws[s] = *elem(w_c, vi + s);
           }
         }
       }
@@ -305,7 +333,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         m.x += quad_xor2(m.x);
         m.y += quad_xor2(m.y);
         mv[s] = ok ? m : make_float2(0.0f, 0.0f);
-        if (!kBufModel && put_model && q == 0 && s < nt) a.model[vi + s] = mv[s];
+        if (!kBufModel && put_model && q == 0 && s < nt) *elem(model_c, vi + s) = mv[s];
       }
       if (MODE != kDegrid && (kAhead || ok || s == 0)) {
         float2 v = vs[s];
@@ -343,7 +371,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     if (MODE == kFused && home && q == 0) chi2 += (double)chi2_seg;
     if (kBufModel && MODE != kGrid && put_model && q == 0) {
       if (vec) {
-        float4 *m4 = reinterpret_cast<float4 *>(a.model + vi);
+        float4 *m4 = reinterpret_cast<float4 *>(elem(model_c, vi));
 #pragma unroll
         for (int h = 0; h < SMAX / 2; ++h) {
           rts_nt_v4f t4 = {mv[2 * h].x, mv[2 * h].y, mv[2 * h + 1].x, mv[2 * h + 1].y};
@@ -352,7 +380,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
       } else {
 #pragma unroll
         for (int s = 0; s < SMAX; ++s)
-          if (s < nt) a.model[vi + s] = mv[s];
+          if (s < nt) *elem(model_c, vi + s) = mv[s];
       }
     }
     if (MODE != kDegrid) {
