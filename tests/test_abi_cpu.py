@@ -74,6 +74,11 @@ def test_size_overflow_rejected(lib):
     p = rts.make_params(256, 10.0, 7, 8, 4096, 130816, 8)
     st, _ = plan_call(lib, p, freq=[150e6] * 4096)
     assert st == 1 and "2^31" in lib.rts_last_error().decode()
+    # one channel of 2^29 samples: within 2^31 overall, beyond the kernels'
+    # 32-bit per-channel byte offsets
+    p = rts.make_params(256, 10.0, 7, 8, 1, 1 << 22, 128)
+    st, _ = plan_call(lib, p, freq=[150e6])
+    assert st == 1 and "n_base*n_time" in lib.rts_last_error().decode()
 
 
 def test_null_arguments_rejected(lib):
