@@ -578,33 +578,39 @@ __global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
 // per track keeps the track's coordinates in registers (no cross-lane work), so
 // each sample's FP64 coordinates are computed once and the listing bookkeeping
 // is done once per track.  Tracks that split into several segments (rare) are
-// walked again from memory with the same greedy rule.
+// walked again from memory with the same greedy rule.  The kernel is built for
+// tracks of up to 4 and up to 8 samples (TR), so short tracks hold half the
+// registers.
 constexpr int kTrackRegs = 8;
 
 typedef double rts_d2_a8 __attribute__((ext_vector_type(2), aligned(8)));
 
 // The T (<= kTrackRegs) weights of track b in channel c (vector loads when T is 4
 // or 8 and the weights are 16-byte aligned; a track then starts 16-byte aligned).
-__device__ __forceinline__ void load_track_weights(const PlanArgs &a, int c, int b, float (&w)[kTrackRegs]) {
+template <int TR>
+__device__ __forceinline__ void load_track_weights(const PlanArgs &a, int c, int b, float (&w)[TR]) {
   const float *p = a.w + ((size_t)c * a.B + b) * a.T;
   float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f), y = x;
   if (a.vec_t) {
     x = reinterpret_cast<const float4 *>(p)[0];
-    if (a.T == 8) y = reinterpret_cast<const float4 *>(p)[1];
+    if (TR == 8 && a.T == 8) y = reinterpret_cast<const float4 *>(p)[1];
   } else {
     if (a.T > 0) x.x = p[0];
     if (a.T > 1) x.y = p[1];
     if (a.T > 2) x.z = p[2];
     if (a.T > 3) x.w = p[3];
-    if (a.T > 4) y.x = p[4];
-    if (a.T > 5) y.y = p[5];
-    if (a.T > 6) y.z = p[6];
-    if (a.T > 7) y.w = p[7];
+    if (TR == 8 && a.T > 4) y.x = p[4];
+    if (TR == 8 && a.T > 5) y.y = p[5];
+    if (TR == 8 && a.T > 6) y.z = p[6];
+    if (TR == 8 && a.T > 7) y.w = p[7];
   }
-  w[0] = x.x; w[1 % kTrackRegs] = x.y; w[2 % kTrackRegs] = x.z; w[3 % kTrackRegs] = x.w;
-  w[4 % kTrackRegs] = y.x; w[5 % kTrackRegs] = y.y; w[6 % kTrackRegs] = y.z; w[7 % kTrackRegs] = y.w;
+  w[0] = x.x; w[1 % TR] = x.y; w[2 % TR] = x.z; w[3 % TR] = x.w;
+  if (TR == 8) {
+    w[4 % TR] = y.x; w[5 % TR] = y.y; w[6 % TR] = y.z; w[7 % TR] = y.w;
+  }
 }
 
+template <int TR>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plan_track_count(PlanArgs a) {
   extern __shared__ uint32_t bins[];                 // [cg][nT2]
   const int c0 = blockIdx.y * a.cg;
@@ -615,14 +621,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   __syncthreads();
   const int64_t ntr = (int64_t)a.ncopy * a.B;
   const int64_t tr_end = min(ntr, (int64_t)bx * a.chunk + a.chunk);
-  unsigned long long nvalid = 0, nflag = 0, noff = 0, nseg = 0, nlist = 0;
+  // per-thread sample counts stay below the plan's 2^31 samples: 32-bit adds
+  uint32_t nvalid = 0, nflag = 0, noff = 0;
+  unsigned long long nseg = 0, nlist = 0;
   for (int64_t tr = (int64_t)bx * a.chunk + threadIdx.x; tr < tr_end; tr += kBlock) {
     const int copy = (int)(tr / a.B);
     const int b = (int)(tr - (int64_t)copy * a.B);
     const double sgn = copy ? -1.0 : 1.0;
-    double u[kTrackRegs], v[kTrackRegs];
+    double u[TR], v[TR];
 #pragma unroll
-    for (int t = 0; t < kTrackRegs; ++t) {
+    for (int t = 0; t < TR; ++t) {
       u[t] = v[t] = 0.0;
       if (t < a.T) {
         // (u, v) of one sample in one 16-byte load (8-byte aligned address)
@@ -632,19 +640,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       }
     }
     // The weights of the next channel are loaded while this one is processed.
-    float wn[kTrackRegs];
+    float wn[TR];
     load_track_weights(a, c0, b, wn);
 #pragma unroll 1
     for (int c = c0; c < c1; ++c) {
-      float wv[kTrackRegs];
+      float wv[TR];
 #pragma unroll
-      for (int t = 0; t < kTrackRegs; ++t) wv[t] = wn[t];
+      for (int t = 0; t < TR; ++t) wv[t] = wn[t];
       if (c + 1 < c1) load_track_weights(a, c + 1, b, wn);
       const double sc = a.scale[c];
-      Sample sm[kTrackRegs];
+      Sample sm[TR];
       int mnx = 1 << 30, mxx = -(1 << 30), mny = 1 << 30, mxy = -(1 << 30);
 #pragma unroll
-      for (int t = 0; t < kTrackRegs; ++t) {
+      for (int t = 0; t < TR; ++t) {
         sm[t].valid = sm[t].flagged = false;
         sm[t].cx = sm[t].cy = sm[t].rx = sm[t].ry = 0;
         if (t < a.T) {
@@ -677,9 +685,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         seg.any = any;
         seg.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
         seg.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
-        uint32_t code[kTrackRegs];
+        uint32_t code[TR];
 #pragma unroll
-        for (int t = 0; t < kTrackRegs; ++t) {
+        for (int t = 0; t < TR; ++t) {
           code[t] = 0u;
           if (t < a.T && sm[t].valid) {
             const int sx = (sm[t].cx - (seg.X0 + a.h_lo)) * a.OS + (sm[t].rx - a.r0);
@@ -687,17 +695,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             code[t] = kCoordValid | (uint32_t)(sy << 7) | (uint32_t)sx;
           }
         }
-        if (a.vec_t && a.T == 8) {
-          *reinterpret_cast<uint4 *>(co) = make_uint4(code[0] | code[1 % kTrackRegs] << 16,
-                                                      code[2 % kTrackRegs] | code[3 % kTrackRegs] << 16,
-                                                      code[4 % kTrackRegs] | code[5 % kTrackRegs] << 16,
-                                                      code[6 % kTrackRegs] | code[7 % kTrackRegs] << 16);
+        if (TR == 8 && a.vec_t && a.T == 8) {
+          *reinterpret_cast<uint4 *>(co) = make_uint4(code[0] | code[1 % TR] << 16,
+                                                      code[2 % TR] | code[3 % TR] << 16,
+                                                      code[4 % TR] | code[5 % TR] << 16,
+                                                      code[6 % TR] | code[7 % TR] << 16);
         } else if (a.vec_t && a.T == 4) {
-          *reinterpret_cast<uint2 *>(co) = make_uint2(code[0] | code[1 % kTrackRegs] << 16,
-                                                      code[2 % kTrackRegs] | code[3 % kTrackRegs] << 16);
+          *reinterpret_cast<uint2 *>(co) = make_uint2(code[0] | code[1 % TR] << 16,
+                                                      code[2 % TR] | code[3 % TR] << 16);
         } else {
 #pragma unroll
-          for (int t = 0; t < kTrackRegs; ++t)
+          for (int t = 0; t < TR; ++t)
             if (t < a.T) co[t] = (uint16_t)code[t];
         }
         a.desc[di] = ((uint32_t)any << kDescAnyBit) | ((uint32_t)seg.Y0 << kRecYShift) | (uint32_t)seg.X0;
@@ -1012,8 +1020,10 @@ hipError_t launch_plan_count(const PlanArgs &a, hipStream_t s) {
   if (a.nbx > 0) {
     dim3 g3((unsigned)a.nbx, (a.C + a.cg - 1) / a.cg);
     const size_t lds = (size_t)a.cg * a.nT2 * sizeof(uint32_t);
-    if (a.T <= kTrackRegs)
-      hipLaunchKernelGGL(k_plan_track_count, g3, dim3(kBlock), lds, s, a);
+    if (a.T <= 4)
+      hipLaunchKernelGGL(k_plan_track_count<4>, g3, dim3(kBlock), lds, s, a);
+    else if (a.T <= kTrackRegs)
+      hipLaunchKernelGGL(k_plan_track_count<kTrackRegs>, g3, dim3(kBlock), lds, s, a);
     else
       hipLaunchKernelGGL(k_plan_chunk<false>, g3, dim3(kBlock), lds, s, a);
     return hipGetLastError();
