@@ -765,8 +765,22 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
   // Channels outermost: the records one workgroup writes for a key form one
   // contiguous run of the work list, and visiting one channel's keys at a time
   // writes each run within a short interval (whole cache lines in L2).
+  // Each thread takes four tracks per pass and loads their descriptors together,
+  // so that the loads overlap instead of each track waiting for its own.
+  constexpr int kUnroll = 4;
   for (int c = c0; c < c1; ++c) {
-    for (int64_t tr = (int64_t)bx * a.chunk + threadIdx.x; tr < tr_end; tr += kBlock) {
+    const uint32_t *desc_c = a.desc + (size_t)c * a.ncopy * a.B;   // [ncopy][B]: index tr
+    for (int64_t tr0 = (int64_t)bx * a.chunk + threadIdx.x; tr0 < tr_end; tr0 += kUnroll * kBlock) {
+    uint32_t dd[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t tr = tr0 + (int64_t)u * kBlock;
+      dd[u] = tr < tr_end ? desc_c[tr] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t tr = tr0 + (int64_t)u * kBlock;
+      if (tr >= tr_end) break;
       const int copy = (int)(tr / a.B);
       const int b = (int)(tr - (int64_t)copy * a.B);
       auto emit = [&](const Seg &seg) {
@@ -778,7 +792,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
             atomicAdd(&a.stats[5], 1ull);
         });
       };
-      const uint32_t d = a.desc[((size_t)c * a.ncopy + copy) * a.B + b];
+      const uint32_t d = dd[u];
       if (d != kDescMulti) {
         Seg seg;
         seg.t0 = 0;
@@ -790,6 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
       } else {
         walk_track(a, c, b, copy, emit);
       }
+    }
     }
   }
 }
