@@ -12,7 +12,9 @@
  * is the adjoint without weights,
  *     M_i = sum_{x,y} k(y - y_i) k(x - x_i) G[c][y][x].
  * Coordinates: x_i = u_i f_c / (c du) + N/2 cells (pixel N/2 is u = 0), snapped to
- * 1/OS cell by rounding half up; this is the only FP64 arithmetic besides the
+ * 1/OS cell by rounding half up, xs = floor(x OS + 1/2), every product and sum
+ * rounded once in FP64 (no fused multiply-add), so the snapped coordinates equal
+ * those of a plain IEEE evaluation bit for bit; this is the only FP64 arithmetic besides the
  * accumulators and chi-squared sums, the rest is FP32 (or the matrix-core forms
  * of rts_precision).  A sample is valid iff its weight (at plan time) is non-zero
  * and every tap lies on the grid; invalid samples contribute nothing and predict 0.
