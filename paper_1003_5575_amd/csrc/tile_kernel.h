@@ -258,6 +258,13 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     // stored together after the sample loop; otherwise each is stored at once.
     constexpr bool kBufModel = BLOCK == 256;
     float2 mv[SMAX];
+    // Otherwise lane q of the quad keeps the model values of samples q, q+4, ...
+    // (every lane holds each value after the reduction) and the quad writes them
+    // after the sample loop, four consecutive samples per store instruction.
+    constexpr int kMine = (SMAX + kGroup - 1) / kGroup;
+    float2 mine[kMine];
+#pragma unroll
+    for (int h = 0; h < kMine; ++h) mine[h] = make_float2(0.0f, 0.0f);
     // The sample loop is straight-line code (no per-sample branches).  The
     // kernel-table rows of sample s+1 are read from LDS before sample s is
     // computed, and a scheduling barrier keeps the compiler from hoisting reads
@@ -333,7 +340,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         m.x += quad_xor2(m.x);
         m.y += quad_xor2(m.y);
         mv[s] = ok ? m : make_float2(0.0f, 0.0f);
-        if (!kBufModel && put_model && q == 0 && s < nt) *elem(model_c, vi + s) = mv[s];
+        if (!kBufModel && q == (s & (kGroup - 1))) mine[s / kGroup] = mv[s];
       }
       if (MODE != kDegrid && (kAhead || ok || s == 0)) {
         float2 v = vs[s];
@@ -369,6 +376,11 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     }
 
     if (MODE == kFused && home && q == 0) chi2 += (double)chi2_seg;
+    if (!kBufModel && MODE != kGrid && put_model) {
+#pragma unroll
+      for (int h = 0; h < kMine; ++h)
+        if (kGroup * h + q < nt) *elem(model_c, vi + kGroup * h + q) = mine[h];
+    }
     if (kBufModel && MODE != kGrid && put_model && q == 0) {
       if (vec) {
         float4 *m4 = reinterpret_cast<float4 *>(elem(model_c, vi));
