@@ -301,13 +301,15 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
       }
     };
     // The straight-line form with reads one sample ahead needs more registers:
-    // only with the 256-register budget.  Otherwise each sample is a branch
-    // (skipped past the segment's end) that reads its own table rows.
+    // only with the 256-register budget.  Otherwise each sample reads its own
+    // table rows; segments of up to 4 samples run every slot (a slot past the
+    // segment's end, or a flagged one, adds zeros), longer ones skip the slots
+    // past the end (the straight-line form spills there).
     constexpr bool kAhead = BLOCK == 256;
     if (kAhead) read_rows(cws[0], kyn, kxn);
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
-      if (!kAhead && s >= nt) continue;
+      if (!kAhead && SMAX > 4 && s >= nt) continue;
       const uint32_t cw = cws[s];
       const bool ok = (cw & kCoordValid) != 0;
       float ky[KYN], kx[CPL];
@@ -342,7 +344,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         mv[s] = ok ? m : make_float2(0.0f, 0.0f);
         if (!kBufModel && q == (s & (kGroup - 1))) mine[s / kGroup] = mv[s];
       }
-      if (MODE != kDegrid && (kAhead || ok || s == 0)) {
+      if (MODE != kDegrid) {
         float2 v = vs[s];
         const float wt = ws[s];
         if (copy) v.y = -v.y;
