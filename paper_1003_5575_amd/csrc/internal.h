@@ -42,7 +42,10 @@ constexpr int kRecAnyBit = 31;
 constexpr uint16_t kCoordValid = 0x8000u;
 
 // Per-track segment descriptor written by the first plan pass (chunked sort):
-// X0 | Y0 << 13 | any << 30 for a track that is one segment, kDescMulti otherwise.
+// X0 | Y0 << 13 | fx << 26 | fy << 27 | any << 30 for a track that is one segment
+// (fx, fy: the window's last column / row holds no taps), kDescMulti otherwise.
+constexpr int kDescFxBit = 26;
+constexpr int kDescFyBit = 27;
 constexpr int kDescAnyBit = 30;
 constexpr uint32_t kDescMulti = 0x80000000u;
 

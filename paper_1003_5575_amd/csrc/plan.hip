@@ -68,7 +68,17 @@ struct Seg {
   int t0, nt;
   bool any;
   int X0, Y0;
+  int fx, fy;   // 1: no sample's taps reach the window's last column (row)
 };
+
+// 1 when no valid sample of a segment reaches the last column (row) of its
+// (W+1)-cell window: its samples sit in one cell column (row) and the window was
+// not shifted at the grid edge, so that column holds zero weights.  A window that
+// crosses a tile edge with that column only is not listed in the next tile,
+// where it would add nothing.
+__device__ __forceinline__ int last_free(const PlanArgs &a, bool any, int X0, int mx) {
+  return (any && mx - a.h_lo + a.W - 1 < X0 + a.WN - 1) ? 1 : 0;
+}
 
 // Walk one baseline track of channel c and emit its segments in time order.  A
 // segment is a run of at most seg_max consecutive samples whose valid samples'
@@ -91,6 +101,8 @@ __device__ __forceinline__ void walk_track(const PlanArgs &a, int c, int b, int 
     sgm.any = any;
     sgm.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
     sgm.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+    sgm.fx = last_free(a, any, sgm.X0, mxx);
+    sgm.fy = last_free(a, any, sgm.Y0, mxy);
     emit(sgm);
   };
   for (int t = 0; t < a.T; ++t) {
@@ -137,11 +149,11 @@ __device__ __forceinline__ void for_listings(const PlanArgs &a, int c, int copy,
   }
   int tx0, tx1, ty0, ty1;
   if (a.log2tile >= 0) {
-    tx0 = sg.X0 >> a.log2tile; tx1 = (sg.X0 + a.WN - 1) >> a.log2tile;
-    ty0 = sg.Y0 >> a.log2tile; ty1 = (sg.Y0 + a.WN - 1) >> a.log2tile;
+    tx0 = sg.X0 >> a.log2tile; tx1 = (sg.X0 + a.WN - 1 - sg.fx) >> a.log2tile;
+    ty0 = sg.Y0 >> a.log2tile; ty1 = (sg.Y0 + a.WN - 1 - sg.fy) >> a.log2tile;
   } else {
-    tx0 = sg.X0 / a.tile; tx1 = (sg.X0 + a.WN - 1) / a.tile;
-    ty0 = sg.Y0 / a.tile; ty1 = (sg.Y0 + a.WN - 1) / a.tile;
+    tx0 = sg.X0 / a.tile; tx1 = (sg.X0 + a.WN - 1 - sg.fx) / a.tile;
+    ty0 = sg.Y0 / a.tile; ty1 = (sg.Y0 + a.WN - 1 - sg.fy) / a.tile;
   }
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx)
@@ -286,13 +298,13 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter(PlanArgs a) {
 // shuffles), so each lane learns the segment it belongs to without a leader; the
 // first lane of each segment emits its listings with global atomics.
 struct LaneSeg {
-  int t0, nt, X0, Y0;
+  int t0, nt, X0, Y0, fx, fy;
   bool any;
   bool single;   // the whole track is this one segment
 };
 
 __device__ __forceinline__ LaneSeg lane_segment(const PlanArgs &a, const Sample &sm, int t, int G) {
-  LaneSeg mine{0, 0, 0, 0, false, false};
+  LaneSeg mine{0, 0, 0, 0, 0, 0, false, false};
   int t0 = 0;
   bool any = false;
   int mnx = 0, mxx = 0, mny = 0, mxy = 0;
@@ -303,6 +315,8 @@ __device__ __forceinline__ LaneSeg lane_segment(const PlanArgs &a, const Sample 
       mine.any = any;
       mine.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
       mine.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+      mine.fx = last_free(a, any, mine.X0, mxx);
+      mine.fy = last_free(a, any, mine.Y0, mxy);
     }
   };
   for (int tt = 0; tt < a.T; ++tt) {
@@ -383,6 +397,8 @@ __device__ __forceinline__ LaneSeg track_segment(const PlanArgs &a, const Sample
     sg.any = any;
     sg.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
     sg.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+    sg.fx = last_free(a, any, sg.X0, mxx);
+    sg.fy = last_free(a, any, sg.Y0, mxy);
     sg.single = true;
     return sg;
   }
@@ -436,6 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_plan_lanes(PlanArgs a) {
     if (t != sg.t0) continue;
     Seg seg;
     seg.t0 = sg.t0; seg.nt = sg.nt; seg.any = sg.any; seg.X0 = sg.X0; seg.Y0 = sg.Y0;
+    seg.fx = sg.fx; seg.fy = sg.fy;
     if (!SCATTER) ++nseg;
     for_listings(a, c, copy, seg, [&](int64_t key, int, int, bool home) {
       if (!SCATTER) {
@@ -534,11 +551,13 @@ __global__ __launch_bounds__(kBlock) void k_plan_chunk(PlanArgs a) {
       }
       if (!SCATTER && t == 0)
         a.desc[((size_t)c * a.ncopy + copy) * a.B + b] =
-            sg.single ? ((uint32_t)sg.any << kDescAnyBit) | ((uint32_t)sg.Y0 << kRecYShift) | (uint32_t)sg.X0
+            sg.single ? ((uint32_t)sg.any << kDescAnyBit) | ((uint32_t)sg.fx << kDescFxBit) |
+                            ((uint32_t)sg.fy << kDescFyBit) | ((uint32_t)sg.Y0 << kRecYShift) | (uint32_t)sg.X0
                       : kDescMulti;
       if (t != sg.t0) continue;
       Seg seg;
       seg.t0 = sg.t0; seg.nt = sg.nt; seg.any = sg.any; seg.X0 = sg.X0; seg.Y0 = sg.Y0;
+      seg.fx = sg.fx; seg.fy = sg.fy;
       if (!SCATTER) ++nseg;
       for_listings(a, c, copy, seg, [&](int64_t key, int, int, bool home) {
         const int bin = (int)(key - (int64_t)c0 * a.nT2);
@@ -685,6 +704,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         seg.any = any;
         seg.X0 = any ? min(mnx - a.h_lo, a.N - a.WN) : 0;
         seg.Y0 = any ? min(mny - a.h_lo, a.N - a.WN) : 0;
+        seg.fx = last_free(a, any, seg.X0, mxx);
+        seg.fy = last_free(a, any, seg.Y0, mxy);
         uint32_t code[TR];
 #pragma unroll
         for (int t = 0; t < TR; ++t) {
@@ -708,7 +729,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
           for (int t = 0; t < TR; ++t)
             if (t < a.T) co[t] = (uint16_t)code[t];
         }
-        a.desc[di] = ((uint32_t)any << kDescAnyBit) | ((uint32_t)seg.Y0 << kRecYShift) | (uint32_t)seg.X0;
+        a.desc[di] = ((uint32_t)any << kDescAnyBit) | ((uint32_t)seg.fx << kDescFxBit) |
+                     ((uint32_t)seg.fy << kDescFyBit) | ((uint32_t)seg.Y0 << kRecYShift) | (uint32_t)seg.X0;
         count(seg);
       } else {
         a.desc[di] = kDescMulti;
@@ -800,6 +822,8 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
         seg.any = (d >> kDescAnyBit) & 1u;
         seg.X0 = (int)(d & kRecXMask);
         seg.Y0 = (int)((d >> kRecYShift) & kRecXMask);
+        seg.fx = (int)((d >> kDescFxBit) & 1u);
+        seg.fy = (int)((d >> kDescFyBit) & 1u);
         emit(seg);
       } else {
         walk_track(a, c, b, copy, emit);
