@@ -254,8 +254,8 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     float2 up[WN][CPL];
 
     float chi2_seg = 0.0f;   // this segment's sum of w |r|^2 (SMAX terms, FP32)
-    // With the 256-register budget the segment's model values are kept and
-    // stored together after the sample loop; otherwise each is stored at once.
+    // With the 256-register budget lane 0 of the quad keeps all of the segment's
+    // model values and stores them after the sample loop as 16-byte vectors.
     constexpr bool kBufModel = BLOCK == 256;
     float2 mv[SMAX];
     // Otherwise lane q of the quad keeps the model values of samples q, q+4, ...
