@@ -83,7 +83,9 @@ def touched_cells(uvw_m, freq_hz, N, du, W, OS):
     return total
 
 
-KERNEL_SOURCES = ("tile_kernel.h", "tile_dispatch.h", "tile_fused.hip", "internal.h")
+# The fused tile kernel's sources, and the plan's (its work list sets how many
+# listings the kernel walks, so a plan change also changes the kernel's traffic).
+KERNEL_SOURCES = ("tile_kernel.h", "tile_dispatch.h", "tile_fused.hip", "internal.h", "plan.hip")
 POLCONV_SOURCES = ("polconv.hip", "internal.h")
 
 
