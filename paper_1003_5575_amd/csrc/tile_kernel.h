@@ -7,9 +7,13 @@
 // list of segments whose (W+1)x(W+1) window touches the tile.  A quad of lanes
 // handles one segment: up to SMAX consecutive samples of one baseline that share
 // the window, so the G_in window and the accumulated update stay in registers
-// across the samples and reach LDS once per segment.  A segment whose window
-// crosses a tile edge is listed in every tile it touches; each copy adds only the
-// cells of its own tile, so every output cell has exactly one writer.
+// across the samples and reach LDS once per segment.  Consecutive samples that
+// snap to the same oversampled position (most of them, since a baseline moves by
+// a small fraction of a cell per time step) share their kernel rows, so the quad
+// computes one degridded value and one outer-product update per run of such
+// samples rather than per sample.  A segment whose window crosses a tile edge is
+// listed in every tile it touches; each copy adds only the cells of its own tile,
+// so every output cell has exactly one writer.
 //
 // Modes:
 //   kGrid:   G_out = sum_s w_s V_s k_y k_x                    (Eq. (1))
@@ -50,6 +54,16 @@ __device__ __forceinline__ float quad_xor1(float v) {
 __device__ __forceinline__ float quad_xor2(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
 }
+// Sum over the quad; every lane gets the same bits ((a+b)+(c+d) in each lane's
+// order, and FP addition commutes).
+__device__ __forceinline__ float quad_sum(float v) {
+  v += quad_xor1(v);
+  return v + quad_xor2(v);
+}
+__device__ __forceinline__ uint32_t quad_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));
+  return max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));
+}
 
 // Element i of a per-channel array: a uniform base and a 32-bit byte offset, so
 // the loads take the scalar-base addressing form (no 64-bit address arithmetic
@@ -66,9 +80,9 @@ __device__ __forceinline__ T *elem(T *base, uint32_t i) {
 // One (channel, tile) of the work: zero the accumulator, walk the tile's work
 // list, write the tile.  tabE must already hold the extended kernel table.
 // 512-thread workgroups (64-cell tiles) take the tile's listings in batches of
-// kSortBatch and visit each batch sorted by the 16 x 16-cell block that holds the
-// window centre (a counting sort in LDS), so that the quads of a wave read
-// overlapping G_in windows and share their cache lines.
+// kSortBatch and visit each batch sorted by the block of tile/kSortSide cells
+// on a side that holds the window centre (a counting sort in LDS), so that the
+// quads of a wave read overlapping G_in windows and share their cache lines.
 constexpr int kSortBatch = 1024;
 #ifndef RTS_SORT_SIDE
 #define RTS_SORT_SIDE 8
@@ -202,13 +216,14 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         }
       }
     }
+    // Packed coordinates of all of the segment's samples (every lane finds the
+    // runs below from them), and the visibilities and weights of this lane's own
+    // samples q, q+4, ...
+    constexpr int kMine = (SMAX + kGroup - 1) / kGroup;
     uint32_t cws[SMAX];
-    float2 vs[SMAX];
-    float ws[SMAX];
-    // A whole track that is one segment starts SMAX-aligned: its coordinates,
-    // visibilities and weights are loaded with 16-byte (or 8-byte) vector loads.
-    const bool vec = a.vec && nt == SMAX;
-    if (vec) {
+    // A whole track that is one segment starts SMAX-aligned: its coordinates are
+    // loaded with one 16-byte (or 8-byte) vector load.
+    if (a.vec && nt == SMAX) {
       if (SMAX == 8) {
         const uint4 c4 = *reinterpret_cast<const uint4 *>(elem(coords_c, ci));
         cws[0] = c4.x & 0xFFFFu; cws[1 % SMAX] = c4.x >> 16;
@@ -220,59 +235,62 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         cws[0] = c2.x & 0xFFFFu; cws[1 % SMAX] = c2.x >> 16;
         cws[2 % SMAX] = c2.y & 0xFFFFu; cws[3 % SMAX] = c2.y >> 16;
       }
-      if (MODE != kDegrid) {
-        const float4 *v4 = reinterpret_cast<const float4 *>(elem(vis_c, vi));
-#pragma unroll
-        for (int h = 0; h < SMAX / 2; ++h) {
-          const float4 t4 = v4[h];
-          vs[2 * h] = make_float2(t4.x, t4.y);
-          vs[2 * h + 1] = make_float2(t4.z, t4.w);
-        }
-        const float4 *w4 = reinterpret_cast<const float4 *>(elem(w_c, vi));
-#pragma unroll
-        for (int h = 0; h < SMAX / 4; ++h) {
-          const float4 t4 = w4[h];
-          ws[4 * h] = t4.x; ws[4 * h + 1] = t4.y; ws[4 * h + 2] = t4.z; ws[4 * h + 3] = t4.w;
-        }
-      }
     } else {
 #pragma unroll
+      for (int s = 0; s < SMAX; ++s) cws[s] = s < nt ? (uint32_t)*elem(coords_c, ci + s) : 0u;
+    }
+    float2 vo[kMine];
+    float wo[kMine];
+#pragma unroll
+    for (int h = 0; h < kMine; ++h) {
+      vo[h] = make_float2(0.0f, 0.0f);
+      wo[h] = 0.0f;
+      const int s = kGroup * h + q;
+      if (MODE != kDegrid && s < nt) {
+        vo[h] = *elem(vis_c, vi + s);
+        wo[h] = *elem(w_c, vi + s);
+      }
+    }
+
+    // Runs.  Samples that snap to the same oversampled position have the same
+    // kernel rows: they share one degridded value, and their gridding terms add up
+    // before the outer product, sum_s w_s r_s k_y k_x = (sum_s w_s r_s) k_y k_x
+    // (Eq. (1) regrouped).  A run is a maximal stretch of consecutive valid
+    // samples with one packed coordinate; an invalid sample belongs to no run and
+    // does not break one.  nrun counts the segment's runs; ko[h] is the run of own
+    // sample h (-1 when it is invalid) and co[h] its packed coordinate.
+    // (With SMAX < kGroup, lanes q >= SMAX own no sample.)
+    int nrun = 0;
+    int ko[kMine];
+    uint32_t co[kMine];
+#pragma unroll
+    for (int h = 0; h < kMine; ++h) {
+      ko[h] = -1;
+      co[h] = 0u;
+    }
+    {
+      uint32_t last = 0u;
+#pragma unroll
       for (int s = 0; s < SMAX; ++s) {
-        cws[s] = 0u;
-        vs[s] = make_float2(0.0f, 0.0f);
-        ws[s] = 0.0f;
-        if (s < nt) {
-          cws[s] = *elem(coords_c, ci + s);
-          if (MODE != kDegrid) {
-            vs[s] = *elem(vis_c, vi + s);
-            ws[s] = *elem(w_c, vi + s);
+        const bool ok = (cws[s] & kCoordValid) != 0;
+        nrun += (ok && cws[s] != last) ? 1 : 0;
+        last = ok ? cws[s] : last;
+#pragma unroll
+        for (int h = 0; h < kMine; ++h) {
+          if (s - kGroup * h >= 0 && s - kGroup * h < kGroup && q == s - kGroup * h) {
+            ko[h] = ok ? nrun - 1 : -1;
+            co[h] = cws[s];
           }
         }
       }
     }
-    // The accumulated update: sample 0 (every segment has one) initialises it.
+    // The accumulated update; run slot 0 (every listed segment has a valid sample)
+    // initialises it.
     float2 up[WN][CPL];
-
-    float chi2_seg = 0.0f;   // this segment's sum of w |r|^2 (SMAX terms, FP32)
-    // With the 256-register budget lane 0 of the quad keeps all of the segment's
-    // model values and stores them after the sample loop as 16-byte vectors.
-    constexpr bool kBufModel = BLOCK == 256;
-    float2 mv[SMAX];
-    // Otherwise lane q of the quad keeps the model values of samples q, q+4, ...
-    // (every lane holds each value after the reduction) and the quad writes them
-    // after the sample loop, four consecutive samples per store instruction.
-    constexpr int kMine = (SMAX + kGroup - 1) / kGroup;
-    float2 mine[kMine];
+    float2 mo[kMine];       // degridded values of the own samples
 #pragma unroll
-    for (int h = 0; h < kMine; ++h) mine[h] = make_float2(0.0f, 0.0f);
-    // The sample loop is straight-line code (no per-sample branches).  The
-    // kernel-table rows of sample s+1 are read from LDS before sample s is
-    // computed, and a scheduling barrier keeps the compiler from hoisting reads
-    // further ahead (which would cost registers).  A slot past the segment's end
-    // has packed coordinates 0 (not valid): it reads table row 0 and
-    // contributes nothing.
+    for (int h = 0; h < kMine; ++h) mo[h] = make_float2(0.0f, 0.0f);
     constexpr int KYN = (WN + 3) & ~3;
-    float kyn[KYN], kxn[CPL];
     auto read_rows = [&](const uint32_t cw, float (&ky)[KYN], float (&kx)[CPL]) {
       const int sx = cw & 0x7F, sy = (cw >> 7) & 0x7F;
       const float4 *ry = reinterpret_cast<const float4 *>(tabE + sy * KYN);   // KYN == WNP, the row stride
@@ -300,29 +318,42 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         for (int i = 0; i < CPL; ++i) kx[i] = (kFullCols || col0 + i < WN) ? rx[i] : 0.0f;
       }
     };
-    // The straight-line form with reads one sample ahead needs more registers:
-    // only with the 256-register budget.  Otherwise each sample reads its own
-    // table rows; segments of up to 4 samples run every slot (a slot past the
-    // segment's end, or a flagged one, adds zeros), longer ones skip the slots
-    // past the end (the straight-line form spills there).
-    constexpr bool kAhead = BLOCK == 256;
-    if (kAhead) read_rows(cws[0], kyn, kxn);
+    // One slot per run; a wave runs as many slots as its segment with the most
+    // runs (a slot past a segment's last run has no members and adds zeros).
+    // reachx / reachy: whether any run's cell is the second one on that axis
+    // (extended-table rows OS..2*OS-1); if none is, the window's last column / row
+    // holds only zero taps and the flush skips it.
+    const int OSh = a.OS2 >> 1;
+    bool reachx = false, reachy = false;
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      if (!kAhead && SMAX > 4 && s >= nt) continue;
-      const uint32_t cw = cws[s];
-      const bool ok = (cw & kCoordValid) != 0;
-      float ky[KYN], kx[CPL];
-      if (kAhead) {
+    for (int r = 0; r < SMAX; ++r) {
+      if (r > 0 && !__any(r < nrun)) break;
+      // The run's coordinate (all of its members have it; the other lanes offer 0)
+      // and, for gridding, its summed weight and weighted visibility, each summed
+      // over the quad.
+      bool mem[kMine];
+      uint32_t cw = 0u;
+      float sw = 0.0f, sx = 0.0f, sy = 0.0f;
 #pragma unroll
-        for (int j = 0; j < KYN; ++j) ky[j] = kyn[j];
-#pragma unroll
-        for (int i = 0; i < CPL; ++i) kx[i] = kxn[i];
-        if (s + 1 < SMAX) read_rows(cws[(s + 1) % SMAX], kyn, kxn);
-        __builtin_amdgcn_sched_barrier(0);
-      } else {
-        read_rows(cw, ky, kx);
+      for (int h = 0; h < kMine; ++h) {
+        mem[h] = ko[h] == r;
+        cw = mem[h] ? co[h] : cw;
+        if (MODE != kDegrid) {
+          sw += mem[h] ? wo[h] : 0.0f;
+          sx += mem[h] ? wo[h] * vo[h].x : 0.0f;
+          sy += mem[h] ? wo[h] * vo[h].y : 0.0f;
+        }
       }
+      cw = quad_max_u32(cw);
+      reachx = reachx || (int)(cw & 0x7F) >= OSh;
+      reachy = reachy || (int)((cw >> 7) & 0x7F) >= OSh;
+      if (MODE != kDegrid) {
+        sw = quad_sum(sw);
+        sx = quad_sum(sx);
+        sy = quad_sum(sy);
+      }
+      float ky[KYN], kx[CPL];
+      read_rows(cw, ky, kx);
 
       float2 m = make_float2(0.0f, 0.0f);
       if (MODE != kGrid) {
@@ -337,36 +368,29 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
           m.x = fmaf(kx[i], hr, m.x);
           m.y = fmaf(kx[i], hi, m.y);
         }
-        m.x += quad_xor1(m.x);
-        m.y += quad_xor1(m.y);
-        m.x += quad_xor2(m.x);
-        m.y += quad_xor2(m.y);
-        mv[s] = ok ? m : make_float2(0.0f, 0.0f);
-        if (!kBufModel && q == (s & (kGroup - 1))) mine[s / kGroup] = mv[s];
+        m.x = quad_sum(m.x);
+        m.y = quad_sum(m.y);
+#pragma unroll
+        for (int h = 0; h < kMine; ++h) mo[h] = mem[h] ? m : mo[h];
       }
       if (MODE != kDegrid) {
-        float2 v = vs[s];
-        const float wt = ws[s];
-        if (copy) v.y = -v.y;
-        float ar, ai;
-        if (MODE == kGrid) {
-          ar = wt * v.x;
-          ai = wt * v.y;
-        } else {
-          const float rr = v.x - m.x, ri = v.y - m.y;
-          ar = wt * rr;
-          ai = wt * ri;
-          const float c2 = wt * fmaf(rr, rr, ri * ri);
-          chi2_seg += ok ? c2 : 0.0f;
+        // The run's gridding weight: sum of w (conj(V) for the -uv copy) less
+        // the degridded value times the summed weight (the summed weighted residual).
+        if (copy) sy = -sy;
+        float ar = sx, ai = sy;
+        if (MODE == kFused) {
+          ar = fmaf(-m.x, sw, sx);
+          ai = fmaf(-m.y, sw, sy);
+          const bool has = r < nrun;
+          ar = has ? ar : 0.0f;
+          ai = has ? ai : 0.0f;
         }
-        ar = ok ? ar : 0.0f;
-        ai = ok ? ai : 0.0f;
 #pragma unroll
         for (int i = 0; i < CPL; ++i) {
           const float br = ar * kx[i], bi = ai * kx[i];
 #pragma unroll
           for (int j = 0; j < WN; ++j) {
-            if (s == 0) {
+            if (r == 0) {
               up[j][i] = make_float2(br * ky[j], bi * ky[j]);
             } else {
               up[j][i].x = fmaf(br, ky[j], up[j][i].x);
@@ -377,25 +401,23 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
       }
     }
 
-    if (MODE == kFused && home && q == 0) chi2 += (double)chi2_seg;
-    if (!kBufModel && MODE != kGrid && put_model) {
+    if (MODE == kFused) {
+      // Chi-squared of the own samples (FP32 per lane, FP64 across listings).
+      float c2 = 0.0f;
+#pragma unroll
+      for (int h = 0; h < kMine; ++h) {
+        const float rr = vo[h].x - mo[h].x;
+        const float ri = (copy ? -vo[h].y : vo[h].y) - mo[h].y;
+        c2 += ko[h] >= 0 ? wo[h] * fmaf(rr, rr, ri * ri) : 0.0f;
+      }
+      if (home) chi2 += (double)c2;
+    }
+    // The quad writes the model values of the segment, four consecutive samples
+    // per store instruction.
+    if (MODE != kGrid && put_model) {
 #pragma unroll
       for (int h = 0; h < kMine; ++h)
-        if (kGroup * h + q < nt) *elem(model_c, vi + kGroup * h + q) = mine[h];
-    }
-    if (kBufModel && MODE != kGrid && put_model && q == 0) {
-      if (vec) {
-        float4 *m4 = reinterpret_cast<float4 *>(elem(model_c, vi));
-#pragma unroll
-        for (int h = 0; h < SMAX / 2; ++h) {
-          rts_nt_v4f t4 = {mv[2 * h].x, mv[2 * h].y, mv[2 * h + 1].x, mv[2 * h + 1].y};
-          __builtin_nontemporal_store(t4, reinterpret_cast<rts_nt_v4f *>(&m4[h]));
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s)
-          if (s < nt) *elem(model_c, vi + s) = mv[s];
-      }
+        if (kGroup * h + q < nt) *elem(model_c, vi + kGroup * h + q) = mo[h];
     }
     if (MODE != kDegrid) {
       // Add this lane's window columns to the tile accumulator.  A wave whose
@@ -405,12 +427,15 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
       const int lx = X0 + col0 - x0, ly = Y0 - y0;
       const bool inside = T >= WN && (unsigned)(X0 - x0) <= (unsigned)(T - WN) && (unsigned)ly <= (unsigned)(T - WN);
       double *row = acc + 2 * (ly * T + lx);      // dereferenced only inside the tile
+      // Cells of the window's last column or row that no run reaches hold exact
+      // zeros and are not added.
       if (__all(inside)) {
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
 #pragma unroll
           for (int i = 0; i < CPL; ++i) {
-            if (kFullCols || col0 + i < WN) {
+            const bool on = (j < WN - 1 || reachy) && (col0 + i < WN - 1 || reachx);
+            if ((kFullCols || col0 + i < WN) && on) {
               atomicAdd(row + 2 * i, (double)up[j][i].x);
               atomicAdd(row + 2 * i + 1, (double)up[j][i].y);
             }
@@ -420,10 +445,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
       } else {
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
-          if ((unsigned)(ly + j) < (unsigned)T) {
+          if ((unsigned)(ly + j) < (unsigned)T && (j < WN - 1 || reachy)) {
 #pragma unroll
             for (int i = 0; i < CPL; ++i) {
-              if ((kFullCols || col0 + i < WN) && (unsigned)(lx + i) < (unsigned)T) {
+              if ((kFullCols || col0 + i < WN) && (col0 + i < WN - 1 || reachx) && (unsigned)(lx + i) < (unsigned)T) {
                 atomicAdd(row + 2 * i, (double)up[j][i].x);
                 atomicAdd(row + 2 * i + 1, (double)up[j][i].y);
               }
