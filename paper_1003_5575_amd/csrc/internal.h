@@ -16,7 +16,13 @@ constexpr int kMaxW = 16;
 constexpr int kMaxWMfma = 24;   // supports up to this on the matrix-core path (BF16x3 plans)
 constexpr int kMaxOS = 64;
 constexpr int kMaxN = 8192;
-constexpr int kMaxTile = 64;     // FP64 tile accumulator: 16*64*64 B = 64 KiB of LDS
+constexpr int kMaxTile = 64;     // FP64 tile accumulator: 16*64*66 B = 66 KiB of LDS
+// The FP64 tile accumulator holds the real and the imaginary parts in two planes of
+// tile rows of tile + kAccPad cells (66 KiB at tile 64).  With the pad, cell (x, y)
+// of a plane lies in LDS bank pair (x + kAccPad*y) mod 32, so the adds of windows
+// in neighbouring rows (a wave's windows are sorted by position) spread over the
+// banks instead of sharing the banks of their columns.
+constexpr int kAccPad = 2;
 constexpr double kCLight = 299792458.0;
 constexpr int kBlock = 256;          // threads per workgroup of every kernel here
 constexpr int kMaxCg = 8;            // most channels one plan workgroup handles

@@ -50,7 +50,7 @@ hipError_t launch_tile_mode(const Plan &P, const TileArgs &a, hipStream_t s, boo
   const int per_cu = (P.tile >= 64) ? 2 : 6;
   const unsigned npers = (unsigned)std::min<int64_t>(P.nkeys, (int64_t)P.n_cu * per_cu);
   size_t lds0 = (size_t)a.OS2 * a.WNP * sizeof(float);
-  if (MODE != kDegrid) lds0 += (size_t)2 * P.tile * P.tile * sizeof(double);
+  if (MODE != kDegrid) lds0 += (size_t)2 * P.tile * (P.tile + kAccPad) * sizeof(double);
   // 512-thread workgroups also hold a sorted batch of listings
   const size_t lds = lds0 + ((P.WN <= 8 && P.tile > 32) ? (size_t)kSortBatch * sizeof(uint2) : 0);
   switch (P.WN * 16 + P.seg_max) {

@@ -38,7 +38,7 @@ typedef float rts_v4f_a8 __attribute__((ext_vector_type(4), aligned(8)));   // 1
 // update in registers, and the degridded value of each sample is the sum of the
 // group's partial sums (butterfly steps inside the group of lanes).
 // Minimum waves per SIMD the register allocation of the tile kernel targets for
-// 128- and 512-thread workgroups (128 registers).  64-cell tiles hold a 64 KiB
+// 128- and 512-thread workgroups (128 registers).  64-cell tiles hold a 66 KiB
 // FP64 accumulator, so at most two of their workgroups share a CU; with windows
 // wider than 8 cells they run 256-thread workgroups (two waves per SIMD) that
 // may use up to 256 registers.
@@ -106,9 +106,11 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
   const int T = a.tile;
   const int x0 = tx * T, y0 = ty * T;
   const int TT = T * T;
+  const int AS = T + kAccPad;            // accumulator row stride (cells)
+  const int PL = T * AS;                 // offset of the imaginary plane
 
   if (MODE != kDegrid) {
-    for (int i = threadIdx.x; i < 2 * TT; i += BLOCK) acc[i] = 0.0;
+    for (int i = threadIdx.x; i < 2 * PL; i += BLOCK) acc[i] = 0.0;
     __syncthreads();
   }
 
@@ -426,7 +428,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
       // for all of its segments (one path per wave instead of both).
       const int lx = X0 + col0 - x0, ly = Y0 - y0;
       const bool inside = T >= WN && (unsigned)(X0 - x0) <= (unsigned)(T - WN) && (unsigned)ly <= (unsigned)(T - WN);
-      double *row = acc + 2 * (ly * T + lx);      // dereferenced only inside the tile
+      double *row = acc + ly * AS + lx;           // real plane; dereferenced only inside the tile
       // Cells of the window's last column or row that no run reaches hold exact
       // zeros and are not added.
       if (__all(inside)) {
@@ -436,11 +438,11 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
           for (int i = 0; i < CPL; ++i) {
             const bool on = (j < WN - 1 || reachy) && (col0 + i < WN - 1 || reachx);
             if ((kFullCols || col0 + i < WN) && on) {
-              atomicAdd(row + 2 * i, (double)up[j][i].x);
-              atomicAdd(row + 2 * i + 1, (double)up[j][i].y);
+              atomicAdd(row + i, (double)up[j][i].x);
+              atomicAdd(row + PL + i, (double)up[j][i].y);
             }
           }
-          row += 2 * T;
+          row += AS;
         }
       } else {
 #pragma unroll
@@ -449,12 +451,12 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
 #pragma unroll
             for (int i = 0; i < CPL; ++i) {
               if ((kFullCols || col0 + i < WN) && (col0 + i < WN - 1 || reachx) && (unsigned)(lx + i) < (unsigned)T) {
-                atomicAdd(row + 2 * i, (double)up[j][i].x);
-                atomicAdd(row + 2 * i + 1, (double)up[j][i].y);
+                atomicAdd(row + i, (double)up[j][i].x);
+                atomicAdd(row + PL + i, (double)up[j][i].y);
               }
             }
           }
-          row += 2 * T;
+          row += AS;
         }
       }
     }
@@ -478,12 +480,12 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
   if (MODE != kDegrid) {
     __syncthreads();
     float4 *out = reinterpret_cast<float4 *>(a.gout);
-    const double4 *src = reinterpret_cast<const double4 *>(acc);
     const int half = T / 2;
     for (int i = threadIdx.x; i < TT / 2; i += BLOCK) {
       const int yy = i / half, xx = i - yy * half;
-      const double4 d = src[i];
-      rts_nt_v4f t4 = {(float)d.x, (float)d.y, (float)d.z, (float)d.w};
+      const double2 re = *reinterpret_cast<const double2 *>(acc + yy * AS + 2 * xx);
+      const double2 im = *reinterpret_cast<const double2 *>(acc + PL + yy * AS + 2 * xx);
+      rts_nt_v4f t4 = {(float)re.x, (float)im.x, (float)re.y, (float)im.y};
       __builtin_nontemporal_store(t4, reinterpret_cast<rts_nt_v4f *>(&out[(((size_t)c * a.N + y0 + yy) * a.N + x0) / 2 + xx]));
     }
   }
@@ -494,8 +496,8 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
   __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK != 256 ? RTS_TILE_WAVES : 2)))
 
 // Shared-memory layout of both launches: the extended kernel table, then the FP64
-// accumulator [tile][tile][2] (kGrid, kFused), then (512-thread workgroups) the
-// sorted batch of listings.  LDS float atomics are an order of
+// accumulator [2][tile][tile + kAccPad] (kGrid, kFused), then (512-thread
+// workgroups) the sorted batch of listings.  LDS float atomics are an order of
 // magnitude slower than FP64 ones on this GPU; FP64 also keeps the tile sums
 // nearly independent of the order the work list is visited in.
 template <int BLOCK, int MODE>
@@ -503,7 +505,7 @@ __device__ __forceinline__ float *load_table(const TileArgs &a, double *&acc, ui
   extern __shared__ float4 smem4[];
   float *tabE = reinterpret_cast<float *>(smem4);     // [2*OS][WNP], rows 16-byte aligned
   acc = reinterpret_cast<double *>(tabE + a.OS2 * a.WNP);
-  sorted = reinterpret_cast<uint2 *>(acc + (MODE != kDegrid ? 2 * a.tile * a.tile : 0));
+  sorted = reinterpret_cast<uint2 *>(acc + (MODE != kDegrid ? 2 * a.tile * (a.tile + kAccPad) : 0));
   for (int i = threadIdx.x; i < a.OS2 * a.WNP; i += BLOCK) tabE[i] = a.tabE[i];
   __syncthreads();
   return tabE;
