@@ -29,6 +29,7 @@ namespace rts {
 // kernel: non-temporal stores keep them from displacing G_in windows and sample
 // data in L2.
 typedef float rts_nt_v4f __attribute__((ext_vector_type(4)));
+typedef float rts_nt_v2f __attribute__((ext_vector_type(2)));
 typedef float rts_v4f_a8 __attribute__((ext_vector_type(4), aligned(8)));   // 16 bytes at an 8-byte boundary
 
 
@@ -80,15 +81,15 @@ __device__ __forceinline__ T *elem(T *base, uint32_t i) {
 // One (channel, tile) of the work: zero the accumulator, walk the tile's work
 // list, write the tile.  tabE must already hold the extended kernel table.
 // 512-thread workgroups (64-cell tiles) take the tile's listings in batches of
-// kSortBatch and visit each batch sorted by the block of tile/kSortSide cells
+// kSortBatch and visit each batch sorted by the block of tile/sort_side cells
 // on a side that holds the window centre (a counting sort in LDS), so that the
 // quads of a wave read overlapping G_in windows and share their cache lines.
+// Bins per tile edge: 8 (8 x 8-cell blocks at tile 64) for segments of up to 4
+// samples, 4 for longer segments (the sizes that measured fastest for each).
 constexpr int kSortBatch = 1024;
-#ifndef RTS_SORT_SIDE
-#define RTS_SORT_SIDE 8
-#endif
-constexpr int kSortSide = RTS_SORT_SIDE;              // bins per tile edge
-constexpr int kSortBins = kSortSide * kSortSide;
+constexpr int kSortBinsMax = 64;
+template <int SMAX>
+constexpr int sort_side() { return SMAX >= 8 ? 4 : 8; }
 template <int BLOCK>
 constexpr bool tile_sorts() { return BLOCK == 512; }
 
@@ -131,7 +132,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
 
   constexpr uint32_t kStride = BLOCK / kGroup;
   constexpr bool kSort = tile_sorts<BLOCK>();
-  __shared__ uint32_t sort_cnt[kSortBins];
+  constexpr int kSortSide = sort_side<SMAX>();
+  constexpr int kSortBins = kSortSide * kSortSide;
+  static_assert(kSortBins <= kSortBinsMax, "sort bins");
+  __shared__ uint32_t sort_cnt[kSortBinsMax];
   for (uint32_t bb = beg;; bb += kSortBatch) {
   uint32_t lo = beg, hi = end;
   if constexpr (kSort) {
@@ -419,7 +423,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     if (MODE != kGrid && put_model) {
 #pragma unroll
       for (int h = 0; h < kMine; ++h)
-        if (kGroup * h + q < nt) *elem(model_c, vi + kGroup * h + q) = mo[h];
+        if (kGroup * h + q < nt) {
+          const rts_nt_v2f t2 = {mo[h].x, mo[h].y};
+          __builtin_nontemporal_store(t2, reinterpret_cast<rts_nt_v2f *>(elem(model_c, vi + kGroup * h + q)));
+        }
     }
     if (MODE != kDegrid) {
       // Add this lane's window columns to the tile accumulator.  A wave whose
