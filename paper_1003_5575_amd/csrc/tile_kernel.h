@@ -162,13 +162,17 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
       }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t run = 0;
-      for (int b = 0; b < kSortBins; ++b) {
-        const uint32_t n = sort_cnt[b];
-        sort_cnt[b] = run;
-        run += n;
+    if (threadIdx.x < 64) {
+      // exclusive scan of the bin counts by one wave (a lane per bin)
+      const int l = threadIdx.x;
+      const uint32_t n = l < kSortBins ? sort_cnt[l] : 0u;
+      uint32_t incl = n;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, 64);
+        if (l >= o) incl += t;
       }
+      if (l < kSortBins) sort_cnt[l] = incl - n;
     }
     __syncthreads();
 #pragma unroll
