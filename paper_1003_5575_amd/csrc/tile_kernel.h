@@ -36,8 +36,8 @@ typedef float rts_v4f_a8 __attribute__((ext_vector_type(4), aligned(8)));   // 1
 // Lanes per segment and window columns per lane.  A group of GROUP adjacent
 // lanes shares one segment; lane q of the group owns window columns q*CPL ..
 // q*CPL+CPL-1, holds those columns of the G_in window and of the accumulated
-// update in registers, and the degridded value of each sample is the sum of the
-// group's partial sums (butterfly steps inside the group of lanes).
+// update in registers, and the degridded value of each run of samples is the sum
+// of the group's partial sums (butterfly steps inside the group of lanes).
 // Minimum waves per SIMD the register allocation of the tile kernel targets for
 // 128- and 512-thread workgroups (128 registers).  64-cell tiles hold a 66 KiB
 // FP64 accumulator, so at most two of their workgroups share a CU; with windows
@@ -206,8 +206,9 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
 
     // Issue every global load of the segment before any arithmetic: this lane's
     // columns of the G_in window first (their addresses need only the listing
-    // record), then the packed coordinates, visibilities and weights of all its
-    // samples, so that the segment waits for one memory round trip.
+    // record), then the packed coordinates of the segment's samples and the
+    // visibilities and weights of this lane's own samples, so that the segment
+    // waits for one memory round trip.
     float2 gw[WN][CPL];
     if (MODE != kGrid) {
       const uint32_t g0 = (uint32_t)(Y0 * a.N + X0 + col0);
