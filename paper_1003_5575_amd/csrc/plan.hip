@@ -791,9 +791,9 @@ __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
   // Channels outermost: the records one workgroup writes for a key form one
   // contiguous run of the work list, and visiting one channel's keys at a time
   // writes each run within a short interval (whole cache lines in L2).
-  // Each thread takes four tracks per pass and loads their descriptors together,
+  // Each thread takes eight tracks per pass and loads their descriptors together,
   // so that the loads overlap instead of each track waiting for its own.
-  constexpr int kUnroll = 4;
+  constexpr int kUnroll = 8;
   for (int c = c0; c < c1; ++c) {
     const uint32_t *desc_c = a.desc + (size_t)c * a.ncopy * a.B;   // [ncopy][B]: index tr
     for (int64_t tr0 = (int64_t)bx * a.chunk + threadIdx.x; tr0 < tr_end; tr0 += kUnroll * kBlock) {
