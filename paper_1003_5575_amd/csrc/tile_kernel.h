@@ -331,6 +331,11 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     };
     // One slot per run; a wave runs as many slots as its segment with the most
     // runs (a slot past a segment's last run has no members and adds zeros).
+    // Windows wider than 8 cells with segments of at most 4 samples run every
+    // slot: without the exit between slots the compiler degrids the next slot
+    // before adding this one's outer product, so the G_in window is dead before
+    // the window update is live and both fit in the registers.
+    constexpr bool kSkipSlots = WN <= 8 || SMAX >= 8;
     // reachx / reachy: whether any run's cell is the second one on that axis
     // (extended-table rows OS..2*OS-1); if none is, the window's last column / row
     // holds only zero taps and the flush skips it.
@@ -338,7 +343,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     bool reachx = false, reachy = false;
 #pragma unroll
     for (int r = 0; r < SMAX; ++r) {
-      if (r > 0 && !__any(r < nrun)) break;
+      if (kSkipSlots && r > 0 && !__any(r < nrun)) break;
       // The run's coordinate (all of its members have it; the other lanes offer 0)
       // and, for gridding, its summed weight and weighted visibility, each summed
       // over the quad.
