@@ -775,12 +775,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // several segments is walked again from uvw and the weights (same greedy rule).
 __global__ __launch_bounds__(kBlock) void k_plan_scatter_tracks(PlanArgs a) {
   extern __shared__ uint32_t bins[];
-  // The chunks of one channel group write adjacent runs of each key's range of
-  // the work list: they are placed on one XCD, so that a cache line shared by two
-  // runs is completed in that XCD's L2 rather than written back in part by two.
-  const int lid = xcd_remap((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
-  const int bx = lid % (int)gridDim.x;
-  const int c0 = (lid / (int)gridDim.x) * a.cg;
+  const int bx = blockIdx.x;
+  const int c0 = blockIdx.y * a.cg;
   const int c1 = min(a.C, c0 + a.cg);
   const int nloc = (c1 - c0) * a.nT2;
   for (int i = threadIdx.x; i < nloc; i += kBlock)
