@@ -209,7 +209,10 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
     // record), then the packed coordinates of the segment's samples and the
     // visibilities and weights of this lane's own samples, so that the segment
     // waits for one memory round trip.
+    // The wave issues them at raised priority, so that its round trip starts
+    // before the other waves' arithmetic.
     float2 gw[WN][CPL];
+    __builtin_amdgcn_s_setprio(2);
     if (MODE != kGrid) {
       const uint32_t g0 = (uint32_t)(Y0 * a.N + X0 + col0);
 #pragma unroll
@@ -262,6 +265,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, const int key, cons
         wo[h] = *elem(w_c, vi + s);
       }
     }
+    __builtin_amdgcn_s_setprio(0);
 
     // Runs.  Samples that snap to the same oversampled position have the same
     // kernel rows: they share one degridded value, and their gridding terms add up
